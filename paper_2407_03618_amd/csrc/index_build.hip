@@ -1,0 +1,726 @@
+// Index build: eager index-time scoring into a token-major sparse matrix.
+//
+// Steps (Section 2 "Calculation of BM25", "Eager index-time scoring", "Efficient Matrix
+// Sparsity"; Section 2.1 for shifted variants):
+//   1. validate offsets and token ids on the device, |D| per document, sum |D| in int64;
+//   2. one 64-bit key per token position: (token << 32) | document;
+//   3. stable LSD radix sort of the keys by the token bits (8-bit digits); positions arrive in
+//      document order, so equal tokens stay ordered by document;
+//   4. run-length encoding of equal keys: one stored pair per distinct (t, D), TF = run length;
+//   5. indptr from the first pair of every token, DF = segment length, IDF in FP64;
+//   6. per-pair score S(t, D) (or S - S_theta) in FP32, rounded to the storage type;
+//   7. skip table of long rows (first entry at or after each document block).
+#include <hip/hip_runtime.h>
+
+#include <algorithm>
+#include <cmath>
+#include <cstdarg>
+#include <cstring>
+#include <memory>
+
+#include "device.hpp"
+#include "internal.hpp"
+#include "scan.hpp"
+
+using namespace bm25dev;
+
+namespace bm25 {
+
+// ------------------------------------------------------------------------------------------
+// Device-wide exclusive scan.
+
+constexpr int kScanThreads = 256;
+constexpr int kScanPerThread = 16;
+constexpr int64_t kScanChunk = kScanThreads * kScanPerThread;
+
+template <typename T>
+__device__ __forceinline__ T shfl_up_t(T v, int o) {
+  const int src = (lane() - o) & 63;
+  if constexpr (sizeof(T) == 8) {
+    return (T)bperm64((uint64_t)v, src);
+  } else {
+    return (T)bperm((uint32_t)v, src);
+  }
+}
+
+// Exclusive scan across a 256-thread block; returns the block total in `total`.
+template <typename T>
+__device__ T block_exclusive_scan(T v, T* lds, T& total) {
+  const int l = lane();
+  const int w = threadIdx.x >> 6;
+  T x = v;
+#pragma unroll
+  for (int o = 1; o < 64; o <<= 1) {
+    T y = shfl_up_t(x, o);
+    if (l >= o) x += y;
+  }
+  if (l == 63) lds[w] = x;
+  __syncthreads();
+  T off = 0, tot = 0;
+#pragma unroll
+  for (int i = 0; i < kScanThreads / 64; ++i) {
+    T t = lds[i];
+    if (i < w) off += t;
+    tot += t;
+  }
+  __syncthreads();
+  total = tot;
+  return x - v + off;
+}
+
+template <typename T>
+__global__ __launch_bounds__(kScanThreads) void k_scan_reduce(const T* in, int64_t n, T* part) {
+  __shared__ T lds[kScanThreads / 64];
+  const int64_t base = (int64_t)blockIdx.x * kScanChunk + (int64_t)threadIdx.x * kScanPerThread;
+  T s = 0;
+#pragma unroll
+  for (int i = 0; i < kScanPerThread; ++i) {
+    int64_t j = base + i;
+    if (j < n) s += in[j];
+  }
+  T tot;
+  (void)block_exclusive_scan(s, lds, tot);
+  if (threadIdx.x == 0) part[blockIdx.x] = tot;
+}
+
+template <typename T>
+__global__ __launch_bounds__(kScanThreads) void k_scan_top(T* part, int64_t nparts, T* total) {
+  __shared__ T lds[kScanThreads / 64];
+  T carry = 0;
+  for (int64_t c = 0; c < nparts; c += kScanChunk) {
+    const int64_t base = c + (int64_t)threadIdx.x * kScanPerThread;
+    T v[kScanPerThread];
+    T s = 0;
+#pragma unroll
+    for (int i = 0; i < kScanPerThread; ++i) {
+      int64_t j = base + i;
+      v[i] = (j < nparts) ? part[j] : (T)0;
+      s += v[i];
+    }
+    T tot;
+    T off = block_exclusive_scan(s, lds, tot) + carry;
+#pragma unroll
+    for (int i = 0; i < kScanPerThread; ++i) {
+      int64_t j = base + i;
+      if (j < nparts) part[j] = off;
+      off += v[i];
+    }
+    carry += tot;
+  }
+  if (threadIdx.x == 0 && total != nullptr) *total = carry;
+}
+
+template <typename T>
+__global__ __launch_bounds__(kScanThreads) void k_scan_apply(const T* in, T* out, int64_t n,
+                                                             const T* part) {
+  __shared__ T lds[kScanThreads / 64];
+  const int64_t base = (int64_t)blockIdx.x * kScanChunk + (int64_t)threadIdx.x * kScanPerThread;
+  T v[kScanPerThread];
+  T s = 0;
+#pragma unroll
+  for (int i = 0; i < kScanPerThread; ++i) {
+    int64_t j = base + i;
+    v[i] = (j < n) ? in[j] : (T)0;
+    s += v[i];
+  }
+  T tot;
+  T off = block_exclusive_scan(s, lds, tot) + part[blockIdx.x];
+#pragma unroll
+  for (int i = 0; i < kScanPerThread; ++i) {
+    int64_t j = base + i;
+    if (j < n) out[j] = off;
+    off += v[i];
+  }
+}
+
+int64_t scan_tmp_elems(int64_t n) { return (n + kScanChunk - 1) / kScanChunk + 1; }
+
+template <typename T>
+hipError_t scan_exclusive(const T* in, T* out, int64_t n, T* tmp, T* total, hipStream_t s) {
+  if (n <= 0) {
+    if (total) return hipMemsetAsync(total, 0, sizeof(T), s);
+    return hipSuccess;
+  }
+  const int64_t nparts = (n + kScanChunk - 1) / kScanChunk;
+  hipLaunchKernelGGL(k_scan_reduce<T>, dim3((unsigned)nparts), dim3(kScanThreads), 0, s, in, n,
+                     tmp);
+  hipLaunchKernelGGL(k_scan_top<T>, dim3(1), dim3(kScanThreads), 0, s, tmp, nparts, total);
+  hipLaunchKernelGGL(k_scan_apply<T>, dim3((unsigned)nparts), dim3(kScanThreads), 0, s, in, out,
+                     n, tmp);
+  return hipGetLastError();
+}
+
+template hipError_t scan_exclusive<uint32_t>(const uint32_t*, uint32_t*, int64_t, uint32_t*,
+                                             uint32_t*, hipStream_t);
+template hipError_t scan_exclusive<int64_t>(const int64_t*, int64_t*, int64_t, int64_t*,
+                                            int64_t*, hipStream_t);
+
+// ------------------------------------------------------------------------------------------
+// Build kernels.
+
+struct BuildStatus {
+  unsigned long long sum_len;
+  unsigned int flags;  // 1: malformed offsets, 2: token id out of range, 4: document too long
+  unsigned int pad;
+};
+
+__device__ __forceinline__ uint64_t wave_sum_u64(uint64_t v) {
+#pragma unroll
+  for (int o = 32; o > 0; o >>= 1) v += bperm64(v, lane() ^ o);
+  return v;
+}
+
+__global__ __launch_bounds__(256) void k_validate(const int32_t* __restrict__ tok, int64_t T,
+                                                  const int64_t* __restrict__ off, int64_t N,
+                                                  int32_t V, int32_t* __restrict__ doclen,
+                                                  BuildStatus* st) {
+  const int64_t gid = (int64_t)blockIdx.x * blockDim.x + threadIdx.x;
+  const int64_t stride = (int64_t)gridDim.x * blockDim.x;
+  uint64_t local = 0;
+  unsigned flags = 0;
+  for (int64_t d = gid; d < N; d += stride) {
+    const int64_t lo = off[d], hi = off[d + 1];
+    const int64_t len = hi - lo;
+    if (len < 0 || lo < 0 || hi > T) flags |= 1u;
+    if (len > (int64_t)INT32_MAX) flags |= 4u;
+    doclen[d] = (int32_t)(len < 0 ? 0 : (len > INT32_MAX ? INT32_MAX : len));
+    local += (uint64_t)(len > 0 ? len : 0);
+  }
+  if (gid == 0 && (off[0] != 0 || off[N] != T)) flags |= 1u;
+  for (int64_t p = gid; p < T; p += stride) {
+    const int32_t t = tok[p];
+    if (t < 0 || t >= V) flags |= 2u;
+  }
+  local = wave_sum_u64(local);
+  if (lane() == 0 && local) atomicAdd(&st->sum_len, (unsigned long long)local);
+  if (flags) atomicOr(&st->flags, flags);
+}
+
+// One key per position: the token in the high half, the document in the low half.
+__global__ __launch_bounds__(256) void k_make_keys(const int32_t* __restrict__ tok,
+                                                   const int64_t* __restrict__ off, int64_t N,
+                                                   uint64_t* __restrict__ keys) {
+  const int64_t nwaves = (int64_t)gridDim.x * (blockDim.x / 64);
+  for (int64_t d = ((int64_t)blockIdx.x * blockDim.x + threadIdx.x) / 64; d < N; d += nwaves) {
+    const int64_t lo = off[d], hi = off[d + 1];
+    for (int64_t p = lo + lane(); p < hi; p += 64)
+      keys[p] = ((uint64_t)(uint32_t)tok[p] << 32) | (uint64_t)(uint32_t)d;
+  }
+}
+
+// Stable LSD radix sort by 8-bit digits of the token. A block owns kRadixBlockItems keys; each of
+// its 4 waves owns a contiguous quarter, so the scatter order is (block, wave, position).
+constexpr int kRadixWaveItems = 64 * 64;
+constexpr int kRadixBlockItems = 4 * kRadixWaveItems;
+
+__device__ __forceinline__ uint64_t match_digit8(uint32_t d) {
+  uint64_t m = ~0ull;
+#pragma unroll
+  for (int b = 0; b < 8; ++b) {
+    const bool bit = (d >> b) & 1u;
+    const uint64_t x = ballot(bit);
+    m &= bit ? x : ~x;
+  }
+  return m;
+}
+
+__global__ __launch_bounds__(256) void k_radix_hist(const uint64_t* __restrict__ keys, int64_t n,
+                                                    int shift, uint32_t* __restrict__ hist,
+                                                    int64_t nblk) {
+  __shared__ uint32_t h[4][256];
+  for (int i = threadIdx.x; i < 1024; i += 256) (&h[0][0])[i] = 0;
+  __syncthreads();
+  const int w = threadIdx.x >> 6;
+  const int l = lane();
+  const int64_t base = (int64_t)blockIdx.x * kRadixBlockItems + (int64_t)w * kRadixWaveItems;
+  for (int r = 0; r < kRadixWaveItems / 64; ++r) {
+    const int64_t i = base + r * 64 + l;
+    const bool valid = i < n;
+    const uint32_t d = valid ? (uint32_t)(keys[i] >> shift) & 255u : 0u;
+    const uint64_t peers = match_digit8(d) & ballot(valid);
+    if (valid && __builtin_ctzll(peers) == l) atomicAdd(&h[w][d], (uint32_t)__popcll(peers));
+  }
+  __syncthreads();
+  for (int i = threadIdx.x; i < 1024; i += 256) {
+    const int ww = i >> 8, d = i & 255;
+    hist[((int64_t)d * nblk + blockIdx.x) * 4 + ww] = h[ww][d];
+  }
+}
+
+__global__ __launch_bounds__(256) void k_radix_scatter(const uint64_t* __restrict__ in,
+                                                       uint64_t* __restrict__ out, int64_t n,
+                                                       int shift,
+                                                       const uint32_t* __restrict__ pos,
+                                                       int64_t nblk) {
+  __shared__ uint32_t run[4][256];
+  for (int i = threadIdx.x; i < 1024; i += 256) {
+    const int ww = i >> 8, d = i & 255;
+    run[ww][d] = pos[((int64_t)d * nblk + blockIdx.x) * 4 + ww];
+  }
+  __syncthreads();
+  const int w = threadIdx.x >> 6;
+  const int l = lane();
+  const int64_t base = (int64_t)blockIdx.x * kRadixBlockItems + (int64_t)w * kRadixWaveItems;
+  const uint64_t lt = lanemask_lt();
+  for (int r = 0; r < kRadixWaveItems / 64; ++r) {
+    const int64_t i = base + r * 64 + l;
+    const bool valid = i < n;
+    const uint64_t key = valid ? in[i] : 0ull;
+    const uint32_t d = (uint32_t)(key >> shift) & 255u;
+    const uint64_t peers = match_digit8(d) & ballot(valid);
+    const uint32_t p0 = run[w][d];
+    if (valid) out[p0 + (uint32_t)__popcll(peers & lt)] = key;
+    if (valid && __builtin_ctzll(peers) == l) run[w][d] = p0 + (uint32_t)__popcll(peers);
+  }
+}
+
+// Run-length encoding of equal keys. Each wave owns kRleWaveItems consecutive keys.
+constexpr int kRleWaveItems = 64 * 32;
+constexpr int kRleBlockItems = 4 * kRleWaveItems;
+
+__global__ __launch_bounds__(256) void k_rle_count(const uint64_t* __restrict__ keys, int64_t n,
+                                                   uint32_t* __restrict__ counts) {
+  const int w = threadIdx.x >> 6;
+  const int l = lane();
+  const int64_t base = (int64_t)blockIdx.x * kRleBlockItems + (int64_t)w * kRleWaveItems;
+  uint32_t c = 0;
+  for (int r = 0; r < kRleWaveItems / 64; ++r) {
+    const int64_t i = base + r * 64 + l;
+    const bool head = i < n && (i == 0 || keys[i] != keys[i - 1]);
+    c += (uint32_t)__popcll(ballot(head));
+  }
+  if (l == 0) counts[(int64_t)blockIdx.x * 4 + w] = c;
+}
+
+__global__ __launch_bounds__(256) void k_rle_write(const uint64_t* __restrict__ keys, int64_t n,
+                                                   const uint32_t* __restrict__ bases,
+                                                   uint64_t* __restrict__ uniq,
+                                                   uint32_t* __restrict__ starts) {
+  const int w = threadIdx.x >> 6;
+  const int l = lane();
+  const int64_t base = (int64_t)blockIdx.x * kRleBlockItems + (int64_t)w * kRleWaveItems;
+  uint32_t run = bases[(int64_t)blockIdx.x * 4 + w];
+  const uint64_t lt = lanemask_lt();
+  for (int r = 0; r < kRleWaveItems / 64; ++r) {
+    const int64_t i = base + r * 64 + l;
+    const uint64_t key = i < n ? keys[i] : 0ull;
+    const bool head = i < n && (i == 0 || key != keys[i - 1]);
+    const uint64_t m = ballot(head);
+    if (head) {
+      const uint32_t j = run + (uint32_t)__popcll(m & lt);
+      uniq[j] = key;
+      starts[j] = (uint32_t)i;
+    }
+    run += (uint32_t)__popcll(m);
+  }
+}
+
+__global__ void k_set_u32(uint32_t* p, uint32_t v) { *p = v; }
+
+// indptr[t] = first stored pair whose token is >= t, for t in [0, V].
+__global__ __launch_bounds__(256) void k_indptr(const uint64_t* __restrict__ uniq, int64_t nnz,
+                                                int32_t V, int64_t* __restrict__ indptr) {
+  const int64_t j = (int64_t)blockIdx.x * blockDim.x + threadIdx.x;
+  if (j > nnz) return;
+  const int64_t cur = (j < nnz) ? (int64_t)(uniq[j] >> 32) : (int64_t)V;
+  const int64_t prev = (j > 0) ? (int64_t)(uniq[j - 1] >> 32) : -1;
+  for (int64_t t = prev + 1; t <= cur; ++t) indptr[t] = j;
+}
+
+// IDF(t, C) in FP64 per variant; the Lucene form is the IDF equation of Section 2.
+__device__ double idf_of(int64_t df, double N, int variant) {
+  if (df <= 0) return 0.0;
+  const double d = (double)df;
+  switch (variant) {
+    case BM25_LUCENE: return log((N - d + 0.5) / (d + 0.5) + 1.0);
+    case BM25_ROBERTSON: return log((N - d + 0.5) / (d + 0.5));
+    case BM25_ATIRE: return log(N / d);
+    case BM25_BM25L: return log((N + 1.0) / (d + 0.5));
+    default: return log((N + 1.0) / d);  // BM25+, TF_ldp
+  }
+}
+
+// S_theta(t) / IDF(t): the score at TF = 0 (Section 2.1); zero for sparse variants.
+__device__ double theta_factor(int variant, double k1, double delta) {
+  switch (variant) {
+    case BM25_BM25PLUS: return delta;
+    case BM25_BM25L: return (k1 + 1.0) * delta / (k1 + delta);
+    case BM25_TFLDP: return 1.0 + log(1.0 + log(delta));
+    default: return 0.0;
+  }
+}
+
+__global__ __launch_bounds__(256) void k_df_idf(const int64_t* __restrict__ indptr, int32_t V,
+                                                double N, int variant, double k1, double delta,
+                                                int32_t* __restrict__ df,
+                                                double* __restrict__ idf,
+                                                double* __restrict__ theta,
+                                                float* __restrict__ theta32,
+                                                uint32_t* __restrict__ is_long) {
+  const int64_t t = (int64_t)blockIdx.x * blockDim.x + threadIdx.x;
+  if (t >= V) return;
+  const int64_t d = indptr[t + 1] - indptr[t];
+  df[t] = (int32_t)d;
+  const double w = idf_of(d, N, variant);
+  idf[t] = w;
+  const double th = (d > 0) ? w * theta_factor(variant, k1, delta) : 0.0;
+  theta[t] = th;
+  theta32[t] = (float)th;
+  is_long[t] = (d >= kLongRow) ? 1u : 0u;
+}
+
+__global__ void k_long_id(const uint32_t* __restrict__ flag, const uint32_t* __restrict__ excl,
+                          int32_t V, int32_t* __restrict__ long_id) {
+  const int64_t t = (int64_t)blockIdx.x * blockDim.x + threadIdx.x;
+  if (t >= V) return;
+  long_id[t] = flag[t] ? (int32_t)excl[t] : -1;
+}
+
+struct ScoreParams {
+  float k1, b, delta, inv_lavg, delta_log0;  // delta_log0 = 1 + ln(delta) (TF_ldp)
+  int variant;
+};
+
+// Stored value per pair divided by IDF: S / IDF for sparse variants, (S - S_theta) / IDF for
+// shifted ones, written in forms free of cancellation (Section 2.1: S_delta = S - S_theta).
+__device__ __forceinline__ float stored_factor(float tf, float len, const ScoreParams& p) {
+  const float norm = (1.0f - p.b) + p.b * (len * p.inv_lavg);
+  switch (p.variant) {
+    case BM25_LUCENE:
+    case BM25_ROBERTSON: return tf / (tf + p.k1 * norm);
+    case BM25_ATIRE: return (p.k1 + 1.0f) * tf / (tf + p.k1 * norm);
+    case BM25_BM25PLUS: return (p.k1 + 1.0f) * tf / (p.k1 * norm + tf);
+    case BM25_BM25L: {
+      const float c = tf / norm;
+      return (p.k1 + 1.0f) * p.k1 * c / ((p.k1 + c + p.delta) * (p.k1 + p.delta));
+    }
+    default: {  // TF_ldp: ln(1 + ln(c + delta)) - ln(1 + ln(delta))
+      const float c = tf / norm;
+      return logf((1.0f + logf(c + p.delta)) / p.delta_log0);
+    }
+  }
+}
+
+template <typename ST>
+__global__ __launch_bounds__(256) void k_score(const uint64_t* __restrict__ uniq,
+                                               const uint32_t* __restrict__ starts, int64_t nnz,
+                                               const int32_t* __restrict__ doclen,
+                                               const double* __restrict__ idf, ScoreParams p,
+                                               int32_t* __restrict__ indices,
+                                               int32_t* __restrict__ tf_out,
+                                               typename ST::T* __restrict__ data) {
+  const int64_t j = (int64_t)blockIdx.x * blockDim.x + threadIdx.x;
+  if (j >= nnz) return;
+  const uint64_t key = uniq[j];
+  const uint32_t t = (uint32_t)(key >> 32);
+  const uint32_t d = (uint32_t)key;
+  const uint32_t tf = starts[j + 1] - starts[j];
+  indices[j] = (int32_t)d;
+  tf_out[j] = (int32_t)tf;
+  const float w = (float)idf[t];
+  data[j] = ST::store(w * stored_factor((float)tf, (float)doclen[d], p));
+}
+
+// Skip table of long rows: skip[lid][b] = offset inside the row of the first entry whose
+// document id is >= b * kSkipBlock (the row length if none), for b in [0, nblocks].
+__global__ __launch_bounds__(256) void k_skip(const uint64_t* __restrict__ uniq, int64_t nnz,
+                                              const int32_t* __restrict__ indices,
+                                              const int64_t* __restrict__ indptr,
+                                              const int32_t* __restrict__ long_id,
+                                              int64_t nblocks, uint32_t* __restrict__ skip) {
+  const int64_t j = (int64_t)blockIdx.x * blockDim.x + threadIdx.x;
+  if (j >= nnz) return;
+  const uint32_t t = (uint32_t)(uniq[j] >> 32);
+  const int32_t lid = long_id[t];
+  if (lid < 0) return;
+  const int64_t lo = indptr[t], hi = indptr[t + 1];
+  uint32_t* row = skip + (int64_t)lid * (nblocks + 1);
+  const int64_t blk = indices[j] / kSkipBlock;
+  const int64_t prev = (j == lo) ? -1 : indices[j - 1] / kSkipBlock;
+  for (int64_t b = prev + 1; b <= blk; ++b) row[b] = (uint32_t)(j - lo);
+  if (j == hi - 1)
+    for (int64_t b = blk + 1; b <= nblocks; ++b) row[b] = (uint32_t)(hi - lo);
+}
+
+static unsigned grid_for(int64_t n, int threads) {
+  int64_t g = (n + threads - 1) / threads;
+  if (g < 1) g = 1;
+  return (unsigned)g;
+}
+
+static int bits_needed(uint32_t x) {
+  int b = 0;
+  while (x) {
+    ++b;
+    x >>= 1;
+  }
+  return b;
+}
+
+size_t store_bytes(int dtype) { return dtype == BM25_F32 ? 4 : 2; }
+
+}  // namespace bm25
+
+using namespace bm25;
+
+extern "C" int bm25_index_build(const int32_t* token_ids, int64_t n_tokens,
+                                const int64_t* doc_offsets, int64_t n_docs, int32_t vocab_size,
+                                const bm25_params* params, void* stream, bm25_index** out) {
+  clear_error();
+  if (!out) return set_error(BM25_E_INVAL, "out is NULL");
+  *out = nullptr;
+  if (!token_ids && n_tokens > 0) return set_error(BM25_E_INVAL, "token_ids is NULL");
+  if (!doc_offsets || !params) return set_error(BM25_E_INVAL, "doc_offsets or params is NULL");
+  if (n_docs < 1 || n_docs > INT32_MAX) return set_error(BM25_E_INVAL, "n_docs out of range");
+  if (n_tokens < 0 || n_tokens >= (int64_t)UINT32_MAX)
+    return set_error(BM25_E_INVAL, "n_tokens out of range");
+  if (vocab_size < 1) return set_error(BM25_E_INVAL, "vocab_size must be >= 1");
+  const bm25_params P = *params;
+  if (!(P.k1 >= 0.0) || !(P.b >= 0.0 && P.b <= 1.0) || !(P.delta >= 0.0) ||
+      !std::isfinite(P.k1) || !std::isfinite(P.delta))
+    return set_error(BM25_E_INVAL, "k1, b or delta out of range");
+  if (P.variant < BM25_LUCENE || P.variant > BM25_TFLDP)
+    return set_error(BM25_E_INVAL, "unknown variant %d", P.variant);
+  if (P.variant == BM25_TFLDP && !(P.delta > std::exp(-1.0)))
+    return set_error(BM25_E_INVAL, "TF_ldp needs delta > 1/e");
+  if (P.store_dtype < BM25_F32 || P.store_dtype > BM25_BF16)
+    return set_error(BM25_E_INVAL, "unknown store dtype %d", P.store_dtype);
+  if (n_tokens == 0) return set_error(BM25_E_INVAL, "sum of |D| is 0: L_avg is undefined");
+
+  hipStream_t s = (hipStream_t)stream;
+  std::unique_ptr<bm25_index> idx(new bm25_index());
+  BM25_HIP(hipGetDevice(&idx->device));
+  idx->n_docs = n_docs;
+  idx->n_tokens = n_tokens;
+  idx->vocab = vocab_size;
+  idx->params = P;
+  const int64_t N = n_docs, T = n_tokens;
+  const int32_t V = vocab_size;
+
+#define BM25_ALLOC(buf, bytes)                                                          \
+  do {                                                                                  \
+    hipError_t e_ = (buf).reserve(bytes);                                               \
+    if (e_ != hipSuccess)                                                               \
+      return set_error(BM25_E_NOMEM, "device allocation of %lld bytes failed: %s",     \
+                       (long long)(bytes), hipGetErrorString(e_));                      \
+  } while (0)
+
+  // 1. validation, |D|, sum |D|
+  DevBuf st;
+  BM25_ALLOC(st, sizeof(BuildStatus));
+  BM25_HIP(hipMemsetAsync(st.ptr, 0, sizeof(BuildStatus), s));
+  BM25_ALLOC(idx->doclen, (size_t)N * 4);
+  {
+    int64_t work = std::max(N, T);
+    unsigned g = (unsigned)std::min<int64_t>(grid_for(work, 256), 8192);
+    hipLaunchKernelGGL(k_validate, dim3(g), dim3(256), 0, s, token_ids, T, doc_offsets, N, V,
+                       idx->doclen.as<int32_t>(), st.as<BuildStatus>());
+    BM25_HIP(hipGetLastError());
+  }
+  BuildStatus hst{};
+  BM25_HIP(hipMemcpyAsync(&hst, st.ptr, sizeof(hst), hipMemcpyDeviceToHost, s));
+  BM25_HIP(hipStreamSynchronize(s));
+  if (hst.flags & 1u) return set_error(BM25_E_RANGE, "document offsets are malformed");
+  if (hst.flags & 4u) return set_error(BM25_E_RANGE, "a document holds more than 2^31-1 tokens");
+  if (hst.flags & 2u) return set_error(BM25_E_RANGE, "a token id lies outside [0, vocab_size)");
+  if (hst.sum_len == 0) return set_error(BM25_E_INVAL, "sum of |D| is 0: L_avg is undefined");
+  idx->sum_len = (int64_t)hst.sum_len;
+  idx->l_avg = (double)idx->sum_len / (double)N;
+
+  // 2. keys
+  DevBuf ka, kb;
+  BM25_ALLOC(ka, (size_t)T * 8);
+  BM25_ALLOC(kb, (size_t)T * 8);
+  hipLaunchKernelGGL(k_make_keys, dim3((unsigned)std::min<int64_t>(grid_for(N * 64, 256), 65536)),
+                     dim3(256), 0, s, token_ids, doc_offsets, N, ka.as<uint64_t>());
+  BM25_HIP(hipGetLastError());
+
+  // 3. stable LSD radix sort by token digits
+  const int tbits = bits_needed((uint32_t)(V - 1));
+  const int passes = (tbits + 7) / 8;
+  const int64_t nblk = (T + kRadixBlockItems - 1) / kRadixBlockItems;
+  const int64_t hn = nblk * 1024;
+  DevBuf hist, tmp;
+  BM25_ALLOC(hist, (size_t)hn * 4);
+  const int64_t nrb = (T + kRleBlockItems - 1) / kRleBlockItems;
+  BM25_ALLOC(tmp, (size_t)std::max({scan_tmp_elems(hn), scan_tmp_elems(T), scan_tmp_elems(V),
+                                    scan_tmp_elems(nrb * 4)}) * 8 + 64);
+  uint64_t* src = ka.as<uint64_t>();
+  uint64_t* dst = kb.as<uint64_t>();
+  for (int pass = 0; pass < passes; ++pass) {
+    const int shift = 32 + 8 * pass;
+    hipLaunchKernelGGL(k_radix_hist, dim3((unsigned)nblk), dim3(256), 0, s, src, T, shift,
+                       hist.as<uint32_t>(), nblk);
+    BM25_HIP(hipGetLastError());
+    BM25_HIP(scan_exclusive<uint32_t>(hist.as<uint32_t>(), hist.as<uint32_t>(), hn,
+                                      tmp.as<uint32_t>(), nullptr, s));
+    hipLaunchKernelGGL(k_radix_scatter, dim3((unsigned)nblk), dim3(256), 0, s, src, dst, T, shift,
+                       hist.as<uint32_t>(), nblk);
+    BM25_HIP(hipGetLastError());
+    std::swap(src, dst);
+  }
+  hist.release();
+
+  // 4. run-length encoding: distinct (t, D) pairs and TF
+  DevBuf counts, total;
+  BM25_ALLOC(counts, (size_t)nrb * 4 * 4);
+  BM25_ALLOC(total, 16);
+  hipLaunchKernelGGL(k_rle_count, dim3((unsigned)nrb), dim3(256), 0, s, src, T,
+                     counts.as<uint32_t>());
+  BM25_HIP(hipGetLastError());
+  BM25_HIP(scan_exclusive<uint32_t>(counts.as<uint32_t>(), counts.as<uint32_t>(), nrb * 4,
+                                    tmp.as<uint32_t>(), total.as<uint32_t>(), s));
+  uint64_t* uniq = dst;  // the other sort buffer
+  DevBuf starts;
+  BM25_ALLOC(starts, ((size_t)T + 1) * 4);
+  hipLaunchKernelGGL(k_rle_write, dim3((unsigned)nrb), dim3(256), 0, s, src, T,
+                     counts.as<uint32_t>(), uniq, starts.as<uint32_t>());
+  BM25_HIP(hipGetLastError());
+  uint32_t nnz32 = 0;
+  BM25_HIP(hipMemcpyAsync(&nnz32, total.ptr, 4, hipMemcpyDeviceToHost, s));
+  BM25_HIP(hipStreamSynchronize(s));
+  const int64_t nnz = nnz32;
+  idx->nnz = nnz;
+  hipLaunchKernelGGL(k_set_u32, dim3(1), dim3(1), 0, s, starts.as<uint32_t>() + nnz, (uint32_t)T);
+  BM25_HIP(hipGetLastError());
+
+  // 5. indptr, DF, IDF, S_theta, long rows
+  BM25_ALLOC(idx->indptr, ((size_t)V + 1) * 8);
+  BM25_ALLOC(idx->df, (size_t)V * 4);
+  BM25_ALLOC(idx->idf, (size_t)V * 8);
+  BM25_ALLOC(idx->theta, (size_t)V * 8);
+  BM25_ALLOC(idx->theta32, (size_t)V * 4);
+  BM25_ALLOC(idx->long_id, (size_t)V * 4);
+  hipLaunchKernelGGL(k_indptr, dim3(grid_for(nnz + 1, 256)), dim3(256), 0, s, uniq, nnz, V,
+                     idx->indptr.as<int64_t>());
+  BM25_HIP(hipGetLastError());
+  DevBuf is_long, long_excl;
+  BM25_ALLOC(is_long, (size_t)V * 4);
+  BM25_ALLOC(long_excl, (size_t)V * 4);
+  hipLaunchKernelGGL(k_df_idf, dim3(grid_for(V, 256)), dim3(256), 0, s,
+                     idx->indptr.as<int64_t>(), V, (double)N, P.variant, P.k1, P.delta,
+                     idx->df.as<int32_t>(), idx->idf.as<double>(), idx->theta.as<double>(),
+                     idx->theta32.as<float>(), is_long.as<uint32_t>());
+  BM25_HIP(hipGetLastError());
+  BM25_HIP(scan_exclusive<uint32_t>(is_long.as<uint32_t>(), long_excl.as<uint32_t>(), V,
+                                    tmp.as<uint32_t>(), total.as<uint32_t>() + 1, s));
+  hipLaunchKernelGGL(k_long_id, dim3(grid_for(V, 256)), dim3(256), 0, s, is_long.as<uint32_t>(),
+                     long_excl.as<uint32_t>(), V, idx->long_id.as<int32_t>());
+  BM25_HIP(hipGetLastError());
+
+  // 6. per-pair scores
+  BM25_ALLOC(idx->indices, (size_t)std::max<int64_t>(nnz, 1) * 4);
+  BM25_ALLOC(idx->tf, (size_t)std::max<int64_t>(nnz, 1) * 4);
+  BM25_ALLOC(idx->data, (size_t)std::max<int64_t>(nnz, 1) * store_bytes(P.store_dtype));
+  ScoreParams sp;
+  sp.k1 = (float)P.k1;
+  sp.b = (float)P.b;
+  sp.delta = (float)P.delta;
+  sp.inv_lavg = (float)(1.0 / idx->l_avg);
+  sp.delta_log0 = (P.variant == BM25_TFLDP) ? (float)(1.0 + std::log(P.delta)) : 1.0f;
+  sp.variant = P.variant;
+  if (nnz > 0) {
+    const unsigned g = grid_for(nnz, 256);
+    switch (P.store_dtype) {
+      case BM25_F32:
+        hipLaunchKernelGGL(k_score<F32>, dim3(g), dim3(256), 0, s, uniq, starts.as<uint32_t>(),
+                           nnz, idx->doclen.as<int32_t>(), idx->idf.as<double>(), sp,
+                           idx->indices.as<int32_t>(), idx->tf.as<int32_t>(),
+                           idx->data.as<float>());
+        break;
+      case BM25_F16:
+        hipLaunchKernelGGL(k_score<F16>, dim3(g), dim3(256), 0, s, uniq, starts.as<uint32_t>(),
+                           nnz, idx->doclen.as<int32_t>(), idx->idf.as<double>(), sp,
+                           idx->indices.as<int32_t>(), idx->tf.as<int32_t>(),
+                           idx->data.as<__half>());
+        break;
+      default:
+        hipLaunchKernelGGL(k_score<BF16>, dim3(g), dim3(256), 0, s, uniq, starts.as<uint32_t>(),
+                           nnz, idx->doclen.as<int32_t>(), idx->idf.as<double>(), sp,
+                           idx->indices.as<int32_t>(), idx->tf.as<int32_t>(),
+                           idx->data.as<uint16_t>());
+    }
+    BM25_HIP(hipGetLastError());
+  }
+
+  // 7. skip table of long rows
+  uint32_t n_long = 0;
+  BM25_HIP(hipMemcpyAsync(&n_long, total.as<uint32_t>() + 1, 4, hipMemcpyDeviceToHost, s));
+  BM25_HIP(hipStreamSynchronize(s));
+  idx->n_long = n_long;
+  idx->n_blocks = (N + kSkipBlock - 1) / kSkipBlock;
+  BM25_ALLOC(idx->skip, (size_t)std::max<int64_t>(1, (int64_t)n_long * (idx->n_blocks + 1)) * 4);
+  if (n_long > 0) {
+    hipLaunchKernelGGL(k_skip, dim3(grid_for(nnz, 256)), dim3(256), 0, s, uniq, nnz,
+                       idx->indices.as<int32_t>(), idx->indptr.as<int64_t>(),
+                       idx->long_id.as<int32_t>(), idx->n_blocks, idx->skip.as<uint32_t>());
+    BM25_HIP(hipGetLastError());
+  }
+  BM25_HIP(hipStreamSynchronize(s));
+#undef BM25_ALLOC
+  *out = idx.release();
+  return BM25_OK;
+}
+
+extern "C" int bm25_index_info(const bm25_index* index, int64_t* n_docs, int32_t* vocab_size,
+                               int64_t* nnz, int64_t* sum_len, double* l_avg,
+                               bm25_params* params) {
+  clear_error();
+  if (!index) return set_error(BM25_E_INVAL, "index is NULL");
+  if (n_docs) *n_docs = index->n_docs;
+  if (vocab_size) *vocab_size = index->vocab;
+  if (nnz) *nnz = index->nnz;
+  if (sum_len) *sum_len = index->sum_len;
+  if (l_avg) *l_avg = index->l_avg;
+  if (params) *params = index->params;
+  return BM25_OK;
+}
+
+extern "C" int bm25_index_export(const bm25_index* index, int64_t* indptr, int32_t* indices,
+                                 int32_t* tf, int32_t* df, double* idf, double* theta,
+                                 void* data, void* stream) {
+  clear_error();
+  if (!index) return set_error(BM25_E_INVAL, "index is NULL");
+  hipStream_t s = (hipStream_t)stream;
+  const size_t V = (size_t)index->vocab, nnz = (size_t)index->nnz;
+  auto cp = [&](void* dst, const void* src, size_t bytes) -> hipError_t {
+    if (!dst || bytes == 0) return hipSuccess;
+    return hipMemcpyAsync(dst, src, bytes, hipMemcpyDeviceToDevice, s);
+  };
+  BM25_HIP(cp(indptr, index->indptr.ptr, (V + 1) * 8));
+  BM25_HIP(cp(indices, index->indices.ptr, nnz * 4));
+  BM25_HIP(cp(tf, index->tf.ptr, nnz * 4));
+  BM25_HIP(cp(df, index->df.ptr, V * 4));
+  BM25_HIP(cp(idf, index->idf.ptr, V * 8));
+  BM25_HIP(cp(theta, index->theta.ptr, V * 8));
+  BM25_HIP(cp(data, index->data.ptr, nnz * store_bytes(index->params.store_dtype)));
+  return BM25_OK;
+}
+
+extern "C" int64_t bm25_index_device_bytes(const bm25_index* index) {
+  if (!index) return 0;
+  const bm25::DevBuf* bufs[] = {&index->indptr, &index->indices, &index->tf, &index->data,
+                                &index->df, &index->idf, &index->theta, &index->theta32,
+                                &index->doclen, &index->long_id, &index->skip};
+  int64_t total = 0;
+  for (auto* b : bufs) total += (int64_t)b->bytes;
+  const bm25::SearchScratch* ss[] = {&index->batch_scratch, &index->plain_scratch};
+  for (auto* s : ss) {
+    const bm25::DevBuf* sb[] = {&s->meta, &s->wave_e0, &s->qstat, &s->entries, &s->members,
+                                &s->cand};
+    for (auto* b : sb) total += (int64_t)b->bytes;
+  }
+  return total;
+}
+
+extern "C" void bm25_index_free(bm25_index* index) {
+  if (!index) return;
+  (void)hipDeviceSynchronize();
+  for (auto& ev : index->timing_events) {
+    (void)hipEventDestroy(ev.first);
+    (void)hipEventDestroy(ev.second);
+  }
+  for (auto* sc : {&index->batch_scratch, &index->plain_scratch})
+    if (sc->host_free) (void)hipEventDestroy(sc->host_free);
+  delete index;
+}

@@ -1,0 +1,180 @@
+// Host-side internals shared by the library's translation units.
+#pragma once
+
+#include <hip/hip_runtime.h>
+
+#include <cstdint>
+#include <cstdio>
+#include <map>
+#include <mutex>
+#include <string>
+#include <vector>
+
+#include "../../include/bm25.h"
+
+namespace bm25 {
+
+// Error plumbing: set_error stores a thread-local message and returns the code.
+int set_error(int code, const char* fmt, ...);
+void clear_error();
+
+struct HipError {
+  hipError_t err;
+  const char* what;
+};
+
+#define BM25_HIP(call)                                                             \
+  do {                                                                             \
+    hipError_t e_ = (call);                                                        \
+    if (e_ != hipSuccess) {                                                        \
+      return ::bm25::set_error(BM25_E_HIP, "%s failed: %s", #call,               \
+                               hipGetErrorString(e_));                             \
+    }                                                                              \
+  } while (0)
+
+// Device buffer owned by the library.
+struct DevBuf {
+  void* ptr = nullptr;
+  size_t bytes = 0;
+  DevBuf() = default;
+  DevBuf(const DevBuf&) = delete;
+  DevBuf& operator=(const DevBuf&) = delete;
+  ~DevBuf() { release(); }
+  void release() {
+    if (ptr) (void)hipFree(ptr);
+    ptr = nullptr;
+    bytes = 0;
+  }
+  // Grows to at least n bytes (contents are not preserved). Returns hipSuccess or the error.
+  hipError_t reserve(size_t n) {
+    if (n <= bytes) return hipSuccess;
+    release();
+    size_t want = n < 256 ? 256 : n;
+    hipError_t e = hipMalloc(&ptr, want);
+    if (e != hipSuccess) {
+      ptr = nullptr;
+      return e;
+    }
+    bytes = want;
+    return hipSuccess;
+  }
+  template <typename T>
+  T* as() const {
+    return static_cast<T*>(ptr);
+  }
+};
+
+// Pinned host buffer owned by the library.
+struct PinnedBuf {
+  void* ptr = nullptr;
+  size_t bytes = 0;
+  PinnedBuf() = default;
+  PinnedBuf(const PinnedBuf&) = delete;
+  PinnedBuf& operator=(const PinnedBuf&) = delete;
+  ~PinnedBuf() { release(); }
+  void release() {
+    if (ptr) (void)hipHostFree(ptr);
+    ptr = nullptr;
+    bytes = 0;
+  }
+  hipError_t reserve(size_t n) {
+    if (n <= bytes) return hipSuccess;
+    release();
+    size_t want = n < 4096 ? 4096 : n;
+    hipError_t e = hipHostMalloc(&ptr, want, hipHostMallocDefault);
+    if (e != hipSuccess) {
+      ptr = nullptr;
+      return e;
+    }
+    bytes = want;
+    return hipSuccess;
+  }
+  template <typename T>
+  T* as() const {
+    return static_cast<T*>(ptr);
+  }
+};
+
+// Documents per skip block. Rows with at least kLongRow entries keep, for every block j, the
+// offset of their first entry whose document id is >= j * kSkipBlock, so a sweep that starts at
+// a block boundary finds its cursor with one load.
+constexpr int64_t kSkipBlock = 1024;
+constexpr int64_t kLongRow = 4096;
+
+// Per-batch device scratch of the search path (grown on demand, reused across calls).
+// `meta` mirrors the pinned staging block written by the host planner:
+//   int64 q_off[n+1] | int32 q_k[n] | int32 tile_q0[n_tiles+1] | int64 tile_e0[n_tiles+1]
+struct SearchScratch {
+  DevBuf meta;
+  DevBuf wave_e0;   // int32[n_tiles * (W+1)]
+  DevBuf qstat;     // int32[n]
+  DevBuf entries;   // planner entries
+  DevBuf members;   // int32 per position
+  DevBuf cand;      // uint64 candidate lists
+  PinnedBuf host;   // staging for the host-side plan
+  hipEvent_t host_free = nullptr;  // the staging buffer may be rewritten once this has fired
+};
+
+struct TileShape {
+  int q_tile = 0;
+  int waves = 0;
+  int doc_tile = 0;
+  int doc_groups = 0;
+  int use_graph = 0;
+};
+
+}  // namespace bm25
+
+struct bm25_index {
+  int device = 0;
+  int64_t n_docs = 0;
+  int64_t n_tokens = 0;
+  int32_t vocab = 0;
+  int64_t nnz = 0;
+  int64_t sum_len = 0;
+  double l_avg = 0.0;
+  bm25_params params{};
+
+  bm25::DevBuf indptr;    // int64[V+1]
+  bm25::DevBuf indices;   // int32[nnz]
+  bm25::DevBuf tf;        // int32[nnz]
+  bm25::DevBuf data;      // store dtype[nnz]
+  bm25::DevBuf df;        // int32[V]
+  bm25::DevBuf idf;       // double[V]
+  bm25::DevBuf theta;     // double[V]
+  bm25::DevBuf theta32;   // float[V]
+  bm25::DevBuf doclen;    // int32[N]
+  bm25::DevBuf long_id;   // int32[V]: index among long rows, or -1
+  bm25::DevBuf skip;      // uint32[n_long][n_blocks+1]
+  int64_t n_long = 0;
+  int64_t n_blocks = 0;   // ceil(N / kSkipBlock)
+
+  bm25::SearchScratch batch_scratch;
+  bm25::SearchScratch plain_scratch;
+
+  bool plan_fixed = false;
+  bm25::TileShape fixed_plan;
+  std::map<uint64_t, bm25::TileShape> tuned;  // shape class -> tuned plan
+
+  bool timing = false;
+  std::vector<std::pair<hipEvent_t, hipEvent_t>> timing_events;
+  double timing_ms = 0.0;
+  int64_t timing_launches = 0;
+
+  std::mutex mu;
+};
+
+namespace bm25 {
+
+// Search entry used by the server (host-planned batches).
+int search_batch_impl(bm25_index* idx, const int32_t* q_ids_dev, const int64_t* q_off_host,
+                      int32_t n, const int32_t* k_host, int32_t k_max, int32_t* out_ids,
+                      float* out_scores, int32_t* out_count, hipStream_t stream,
+                      SearchScratch& scratch, const TileShape* force);
+
+size_t search_scratch_bytes(const bm25_index* idx, int32_t n, int64_t positions, int32_t k_max,
+                            const TileShape& shape);
+
+TileShape choose_shape(const bm25_index* idx, int32_t n, int32_t max_qlen, int32_t k_max);
+
+}  // namespace bm25

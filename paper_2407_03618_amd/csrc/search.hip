@@ -1,0 +1,576 @@
+// Host side of the search path: argument checks, tile planning, staging and launches.
+#define BM25_SEARCH_MAIN 1
+#include <hip/hip_runtime.h>
+
+#include <algorithm>
+#include <chrono>
+#include <cmath>
+#include <cstring>
+#include <vector>
+
+#include "internal.hpp"
+#include "search_kernels.hpp"
+
+namespace bm25 {
+
+using namespace bm25dev;
+
+hipError_t launch_gather_f32(int, int, int, dim3, size_t, hipStream_t, const GatherArgs&);
+hipError_t launch_gather_f16(int, int, int, dim3, size_t, hipStream_t, const GatherArgs&);
+hipError_t launch_gather_bf16(int, int, int, dim3, size_t, hipStream_t, const GatherArgs&);
+hipError_t launch_sweep_f32(int, int, dim3, size_t, hipStream_t, const SweepArgs&);
+hipError_t launch_sweep_f16(int, int, dim3, size_t, hipStream_t, const SweepArgs&);
+hipError_t launch_sweep_bf16(int, int, dim3, size_t, hipStream_t, const SweepArgs&);
+
+static constexpr int64_t kMaxLdsBytes = 160 * 1024;
+
+static hipError_t launch_gather(int dtype, int W, int QPW, int KPL, dim3 g, size_t sh,
+                                hipStream_t s, const GatherArgs& a) {
+  switch (dtype) {
+    case BM25_F32: return launch_gather_f32(W, QPW, KPL, g, sh, s, a);
+    case BM25_F16: return launch_gather_f16(W, QPW, KPL, g, sh, s, a);
+    default: return launch_gather_bf16(W, QPW, KPL, g, sh, s, a);
+  }
+}
+
+static hipError_t launch_sweep(int dtype, int W, int KPL, dim3 g, size_t sh, hipStream_t s,
+                               const SweepArgs& a) {
+  switch (dtype) {
+    case BM25_F32: return launch_sweep_f32(W, KPL, g, sh, s, a);
+    case BM25_F16: return launch_sweep_f16(W, KPL, g, sh, s, a);
+    default: return launch_sweep_bf16(W, KPL, g, sh, s, a);
+  }
+}
+
+static hipError_t launch_merge(int KPL, dim3 g, hipStream_t s, const MergeArgs& a) {
+  switch (KPL) {
+    case 1: hipLaunchKernelGGL(k_merge<1>, g, dim3(256), 0, s, a); break;
+    case 2: hipLaunchKernelGGL(k_merge<2>, g, dim3(256), 0, s, a); break;
+    case 4: hipLaunchKernelGGL(k_merge<4>, g, dim3(256), 0, s, a); break;
+    case 8: hipLaunchKernelGGL(k_merge<8>, g, dim3(256), 0, s, a); break;
+    case 16: hipLaunchKernelGGL(k_merge<16>, g, dim3(256), 0, s, a); break;
+    default: return hipErrorInvalidValue;
+  }
+  return hipGetLastError();
+}
+
+static int kpl_for(int k_max) {
+  int kpl = 1;
+  while (kpl * 64 < k_max) kpl *= 2;
+  return kpl;
+}
+
+static IndexView index_view(const bm25_index* idx) {
+  IndexView v;
+  v.indptr = idx->indptr.as<int64_t>();
+  v.indices = idx->indices.as<int32_t>();
+  v.data = idx->data.ptr;
+  v.long_id = idx->long_id.as<int32_t>();
+  v.skip = idx->skip.as<uint32_t>();
+  const int var = idx->params.variant;
+  const bool shifted = var == BM25_BM25L || var == BM25_BM25PLUS || var == BM25_TFLDP;
+  v.theta32 = shifted ? idx->theta32.as<float>() : nullptr;
+  v.n_docs = idx->n_docs;
+  v.n_blocks = idx->n_blocks;
+  v.vocab = idx->vocab;
+  return v;
+}
+
+struct BatchInfo {
+  int32_t max_qlen = 0;
+  int64_t positions = 0;
+};
+
+static int check_batch(const bm25_index* idx, const int32_t* q_ids, const int64_t* q_off,
+                       int32_t n, const int32_t* k, int32_t k_max, const int32_t* out_ids,
+                       const float* out_scores, const int32_t* out_count, BatchInfo& info) {
+  if (!idx) return set_error(BM25_E_INVAL, "index is NULL");
+  if (n < 0) return set_error(BM25_E_INVAL, "n_queries < 0");
+  if (k_max < 1 || k_max > BM25_MAX_K)
+    return set_error(BM25_E_INVAL, "k_max must lie in [1, %d]", BM25_MAX_K);
+  if (n == 0) return BM25_OK;
+  if (!q_off) return set_error(BM25_E_INVAL, "q_offsets is NULL");
+  if (!out_ids || !out_scores || !out_count) return set_error(BM25_E_INVAL, "output is NULL");
+  if (q_off[0] != 0) return set_error(BM25_E_INVAL, "q_offsets[0] must be 0");
+  int64_t mx = 0;
+  for (int32_t i = 0; i < n; ++i) {
+    const int64_t len = q_off[i + 1] - q_off[i];
+    if (len < 0) return set_error(BM25_E_INVAL, "q_offsets must be non-decreasing");
+    if (len > BM25_MAX_QUERY_LEN)
+      return set_error(BM25_E_INVAL, "query %d has %lld ids (limit %d)", i, (long long)len,
+                       BM25_MAX_QUERY_LEN);
+    mx = std::max(mx, len);
+  }
+  if (q_off[n] > (int64_t)INT32_MAX) return set_error(BM25_E_INVAL, "too many query positions");
+  if (q_off[n] > 0 && !q_ids) return set_error(BM25_E_INVAL, "q_ids is NULL");
+  if (k) {
+    for (int32_t i = 0; i < n; ++i)
+      if (k[i] < 1 || k[i] > k_max)
+        return set_error(BM25_E_INVAL, "k[%d] = %d outside [1, k_max]", i, k[i]);
+  }
+  info.max_qlen = (int32_t)mx;
+  info.positions = q_off[n];
+  return BM25_OK;
+}
+
+static bool shape_ok(const TileShape& t, int k_max) {
+  if (!(t.waves == 4 || t.waves == 8)) return false;
+  if (t.q_tile < 1 || t.q_tile > 64 || t.q_tile % t.waves != 0) return false;
+  const int qpw = t.q_tile / t.waves;
+  if (!(qpw == 1 || qpw == 2 || qpw == 4)) return false;
+  if (t.doc_tile < 256 || t.doc_tile > 16384 || t.doc_tile % 256 != 0) return false;
+  if (t.doc_groups < 1 || t.doc_groups > 65536) return false;
+  (void)k_max;
+  return true;
+}
+
+static int64_t gather_lds(const TileShape& t, int64_t ecap) {
+  return (int64_t)t.q_tile * t.doc_tile * 4 + ecap * 4;
+}
+
+TileShape choose_shape(const bm25_index* idx, int32_t n, int32_t max_qlen, int32_t k_max) {
+  TileShape t;
+  const int kpl = kpl_for(k_max);
+  t.waves = 8;
+  t.q_tile = (kpl >= 8) ? 8 : 16;
+  t.doc_tile = 1024;
+  const int64_t ntiles = std::max<int64_t>(1, (n + t.q_tile - 1) / t.q_tile);
+  int64_t g = (1024 + ntiles - 1) / ntiles;
+  g = ((g + 7) / 8) * 8;
+  g = std::min<int64_t>(std::max<int64_t>(g, 8), 512);
+  g = std::min<int64_t>(g, std::max<int64_t>(1, idx->n_blocks));
+  t.doc_groups = (int)g;
+  // keep the accumulator plus cursor slots within the LDS budget for long queries
+  const int64_t ecap = std::min<int64_t>((int64_t)t.q_tile * max_qlen, kTileMaxPositions) + 16;
+  while (gather_lds(t, ecap) > 96 * 1024 && t.doc_tile > 256) t.doc_tile /= 2;
+  t.use_graph = 0;
+  return t;
+}
+
+static uint64_t shape_class(int32_t n, int32_t max_qlen, int32_t k_max) {
+  auto lg = [](int64_t v) {
+    int b = 0;
+    while ((1ll << b) < v) ++b;
+    return (uint64_t)b;
+  };
+  return (lg(n) << 32) | (lg(max_qlen) << 16) | (uint64_t)kpl_for(k_max);
+}
+
+template <typename T>
+static T* carve(uint8_t*& p, size_t count) {
+  uintptr_t u = ((uintptr_t)p + 15) & ~(uintptr_t)15;
+  T* r = reinterpret_cast<T*>(u);
+  p = reinterpret_cast<uint8_t*>(u + count * sizeof(T));
+  return r;
+}
+
+struct Staged {
+  int64_t* q_off;
+  int32_t* q_k;
+  int32_t* tile_q0;
+  int64_t* tile_e0;
+};
+
+// Lays out (q_off, q_k, tile_q0, tile_e0) in `base`; returns the byte size.
+static size_t stage_layout(uint8_t* base, int32_t n, int32_t n_tiles, Staged& s) {
+  uint8_t* p = base;
+  s.q_off = carve<int64_t>(p, (size_t)n + 1);
+  s.q_k = carve<int32_t>(p, (size_t)n);
+  s.tile_q0 = carve<int32_t>(p, (size_t)n_tiles + 1);
+  s.tile_e0 = carve<int64_t>(p, (size_t)n_tiles + 1);
+  return (size_t)(p - base) + 16;
+}
+
+#define BM25_RESERVE(buf, bytes)                                                       \
+  do {                                                                                 \
+    hipError_t e_ = (buf).reserve(bytes);                                              \
+    if (e_ != hipSuccess)                                                              \
+      return set_error(BM25_E_NOMEM, "allocation of %lld bytes failed: %s",           \
+                       (long long)(bytes), hipGetErrorString(e_));                     \
+  } while (0)
+
+// Copies the host plan (offsets, k, tiles) to the device through the pinned staging block.
+static int upload_plan(SearchScratch& sc, hipStream_t s, int32_t n, int32_t n_tiles,
+                       const int64_t* q_off, const int32_t* k, int32_t k_max,
+                       const std::vector<int32_t>& tile_q0, const std::vector<int64_t>& tile_e0,
+                       Staged& dev) {
+  if (!sc.host_free) BM25_HIP(hipEventCreateWithFlags(&sc.host_free, hipEventDisableTiming));
+  else BM25_HIP(hipEventSynchronize(sc.host_free));
+  Staged hs;
+  const size_t bytes = stage_layout(nullptr, n, n_tiles, hs) + 64;
+  BM25_RESERVE(sc.host, bytes);
+  BM25_RESERVE(sc.meta, bytes);
+  stage_layout(sc.host.as<uint8_t>(), n, n_tiles, hs);
+  stage_layout(sc.meta.as<uint8_t>(), n, n_tiles, dev);
+  std::memcpy(hs.q_off, q_off, ((size_t)n + 1) * 8);
+  if (k) std::memcpy(hs.q_k, k, (size_t)n * 4);
+  else for (int32_t i = 0; i < n; ++i) hs.q_k[i] = k_max;
+  std::memcpy(hs.tile_q0, tile_q0.data(), ((size_t)n_tiles + 1) * 4);
+  std::memcpy(hs.tile_e0, tile_e0.data(), ((size_t)n_tiles + 1) * 8);
+  BM25_HIP(hipMemcpyAsync(sc.meta.ptr, sc.host.ptr, bytes, hipMemcpyHostToDevice, s));
+  BM25_HIP(hipEventRecord(sc.host_free, s));
+  return BM25_OK;
+}
+
+static int timed_begin(bm25_index* idx, hipStream_t s, hipEvent_t* b) {
+  *b = nullptr;
+  if (!idx->timing) return BM25_OK;
+  BM25_HIP(hipEventCreate(b));
+  BM25_HIP(hipEventRecord(*b, s));
+  return BM25_OK;
+}
+
+static int timed_end(bm25_index* idx, hipStream_t s, hipEvent_t b) {
+  if (!b) return BM25_OK;
+  hipEvent_t e;
+  BM25_HIP(hipEventCreate(&e));
+  BM25_HIP(hipEventRecord(e, s));
+  idx->timing_events.emplace_back(b, e);
+  return BM25_OK;
+}
+
+int search_batch_impl(bm25_index* idx, const int32_t* q_ids, const int64_t* q_off, int32_t n,
+                      const int32_t* k, int32_t k_max, int32_t* out_ids, float* out_scores,
+                      int32_t* out_count, hipStream_t s, SearchScratch& sc,
+                      const TileShape* force) {
+  BatchInfo info;
+  int rc = check_batch(idx, q_ids, q_off, n, k, k_max, out_ids, out_scores, out_count, info);
+  if (rc != BM25_OK || n == 0) return rc;
+  TileShape t;
+  if (force) {
+    t = *force;
+  } else if (idx->plan_fixed) {
+    t = idx->fixed_plan;
+  } else {
+    auto it = idx->tuned.find(shape_class(n, info.max_qlen, k_max));
+    t = (it != idx->tuned.end()) ? it->second : choose_shape(idx, n, info.max_qlen, k_max);
+  }
+  if (!shape_ok(t, k_max)) return set_error(BM25_E_INVAL, "invalid launch shape");
+  // register budget: at most 8 list registers (QPW * KPL) per lane
+  while ((t.q_tile / t.waves) * kpl_for(k_max) > 8 && t.q_tile > t.waves) t.q_tile /= 2;
+  const int W = t.waves, QPW = t.q_tile / t.waves, KPL = kpl_for(k_max), KP = 64 * KPL;
+
+  // query tiles: up to q_tile consecutive queries and kTileMaxPositions positions
+  std::vector<int32_t> tile_q0;
+  std::vector<int64_t> tile_e0;
+  tile_q0.reserve(n / t.q_tile + 2);
+  tile_e0.reserve(n / t.q_tile + 2);
+  int64_t ent = 0, ecap = 0;
+  int32_t q = 0;
+  while (q < n) {
+    tile_q0.push_back(q);
+    tile_e0.push_back(ent);
+    int64_t pos = 0;
+    int cnt = 0;
+    while (q < n && cnt < t.q_tile && pos + (q_off[q + 1] - q_off[q]) <= kTileMaxPositions) {
+      pos += q_off[q + 1] - q_off[q];
+      ++q;
+      ++cnt;
+    }
+    ent += pos + W;
+    ecap = std::max<int64_t>(ecap, pos + W);
+  }
+  const int32_t n_tiles = (int32_t)tile_q0.size();
+  tile_q0.push_back(n);
+  tile_e0.push_back(ent);
+
+  const int64_t lds = gather_lds(t, ecap);
+  if (lds > kMaxLdsBytes) return set_error(BM25_E_INVAL, "launch shape exceeds LDS");
+  const int64_t G = t.doc_groups;
+  const int64_t nb = std::max<int64_t>(1, idx->n_blocks);
+  const int64_t group_docs = ((nb + G - 1) / G) * kSkipBlock;
+
+  BM25_RESERVE(sc.wave_e0, (size_t)n_tiles * (W + 1) * 4);
+  BM25_RESERVE(sc.qstat, (size_t)n * 4);
+  BM25_RESERVE(sc.entries, (size_t)std::max<int64_t>(ent, 1) * sizeof(Entry));
+  BM25_RESERVE(sc.members, (size_t)std::max<int64_t>(info.positions, 1) * 4);
+  BM25_RESERVE(sc.cand, (size_t)n * G * KP * 8);
+
+  Staged dev;
+  rc = upload_plan(sc, s, n, n_tiles, q_off, k, k_max, tile_q0, tile_e0, dev);
+  if (rc != BM25_OK) return rc;
+
+  IndexView ix = index_view(idx);
+  BatchView bv;
+  bv.q_ids = q_ids;
+  bv.q_off = dev.q_off;
+  bv.q_k = dev.q_k;
+  bv.q_stat = sc.qstat.as<int32_t>();
+  bv.tile_q0 = dev.tile_q0;
+  bv.tile_e0 = dev.tile_e0;
+  bv.wave_e0 = sc.wave_e0.as<int32_t>();
+  bv.entries = sc.entries.as<Entry>();
+  bv.members = sc.members.as<int32_t>();
+  bv.n_queries = n;
+  bv.n_tiles = n_tiles;
+
+  hipLaunchKernelGGL(k_plan, dim3(n_tiles), dim3(kPlanThreads), 0, s, ix, bv, W);
+  BM25_HIP(hipGetLastError());
+
+  GatherArgs ga;
+  ga.ix = ix;
+  ga.bv = bv;
+  ga.cand = sc.cand.as<uint64_t>();
+  ga.group_docs = group_docs;
+  ga.n_groups = (int32_t)G;
+  ga.doc_tile = t.doc_tile;
+  ga.ecap = (int32_t)ecap;
+  hipEvent_t tb;
+  rc = timed_begin(idx, s, &tb);
+  if (rc != BM25_OK) return rc;
+  BM25_HIP(launch_gather(idx->params.store_dtype, W, QPW, KPL,
+                         dim3((unsigned)((int64_t)n_tiles * G)), (size_t)lds, s, ga));
+  rc = timed_end(idx, s, tb);
+  if (rc != BM25_OK) return rc;
+
+  MergeArgs ma;
+  ma.cand = sc.cand.as<uint64_t>();
+  ma.q_ids = q_ids;
+  ma.q_off = dev.q_off;
+  ma.q_k = dev.q_k;
+  ma.q_stat = sc.qstat.as<int32_t>();
+  ma.theta32 = ix.theta32;
+  ma.out_ids = out_ids;
+  ma.out_scores = out_scores;
+  ma.out_count = out_count;
+  ma.n_docs = idx->n_docs;
+  ma.lists = (int32_t)G;
+  ma.k_max = k_max;
+  ma.q_first = 0;
+  BM25_HIP(launch_merge(KPL, dim3(n), s, ma));
+  return BM25_OK;
+}
+
+int search_plain_impl(bm25_index* idx, const int32_t* q_ids, const int64_t* q_off, int32_t n,
+                      const int32_t* k, int32_t k_max, int32_t* out_ids, float* out_scores,
+                      int32_t* out_count, hipStream_t s) {
+  BatchInfo info;
+  int rc = check_batch(idx, q_ids, q_off, n, k, k_max, out_ids, out_scores, out_count, info);
+  if (rc != BM25_OK || n == 0) return rc;
+  SearchScratch& sc = idx->plain_scratch;
+  const int KPL = kpl_for(k_max), KP = 64 * KPL;
+  int W = 8;
+  int DT = std::max(1024, 2 * KP);
+  const int64_t ecap = (int64_t)info.max_qlen + 1;
+  while ((int64_t)W * DT * 4 + (int64_t)W * ecap * 4 > kMaxLdsBytes && W > 4) W /= 2;
+  const int64_t lds = (int64_t)W * DT * 4 + (int64_t)W * ecap * 4;
+  if (lds > kMaxLdsBytes) return set_error(BM25_E_INVAL, "query too long for the per-query form");
+  const int64_t nb = std::max<int64_t>(1, idx->n_blocks);
+  const int64_t blocks_per_sweep = std::max<int64_t>(1, (nb + 2047) / 2048);
+  const int64_t sweep_docs = blocks_per_sweep * kSkipBlock;
+  const int64_t sweepers = (idx->n_docs + sweep_docs - 1) / sweep_docs;
+  const int64_t G = (sweepers + W - 1) / W;
+
+  std::vector<int32_t> tile_q0(n + 1);
+  std::vector<int64_t> tile_e0(n + 1);
+  int64_t ent = 0;
+  for (int32_t i = 0; i < n; ++i) {
+    tile_q0[i] = i;
+    tile_e0[i] = ent;
+    ent += (q_off[i + 1] - q_off[i]) + 1;
+  }
+  tile_q0[n] = n;
+  tile_e0[n] = ent;
+
+  BM25_RESERVE(sc.wave_e0, (size_t)n * 2 * 4);
+  BM25_RESERVE(sc.qstat, (size_t)n * 4);
+  BM25_RESERVE(sc.entries, (size_t)std::max<int64_t>(ent, 1) * sizeof(Entry));
+  BM25_RESERVE(sc.members, (size_t)std::max<int64_t>(info.positions, 1) * 4);
+  BM25_RESERVE(sc.cand, (size_t)G * KP * 8);
+  Staged dev;
+  rc = upload_plan(sc, s, n, n, q_off, k, k_max, tile_q0, tile_e0, dev);
+  if (rc != BM25_OK) return rc;
+
+  IndexView ix = index_view(idx);
+  BatchView bv;
+  bv.q_ids = q_ids;
+  bv.q_off = dev.q_off;
+  bv.q_k = dev.q_k;
+  bv.q_stat = sc.qstat.as<int32_t>();
+  bv.tile_q0 = dev.tile_q0;
+  bv.tile_e0 = dev.tile_e0;
+  bv.wave_e0 = sc.wave_e0.as<int32_t>();
+  bv.entries = sc.entries.as<Entry>();
+  bv.members = sc.members.as<int32_t>();
+  bv.n_queries = n;
+  bv.n_tiles = n;
+  hipLaunchKernelGGL(k_plan, dim3(n), dim3(kPlanThreads), 0, s, ix, bv, 1);
+  BM25_HIP(hipGetLastError());
+
+  SweepArgs sa;
+  sa.ix = ix;
+  sa.bv = bv;
+  sa.cand = sc.cand.as<uint64_t>();
+  sa.sweep_docs = sweep_docs;
+  sa.n_groups = (int32_t)G;
+  sa.doc_tile = DT;
+  sa.ecap = (int32_t)ecap;
+  MergeArgs ma;
+  ma.cand = sc.cand.as<uint64_t>();
+  ma.q_ids = q_ids;
+  ma.q_off = dev.q_off;
+  ma.q_k = dev.q_k;
+  ma.q_stat = sc.qstat.as<int32_t>();
+  ma.theta32 = ix.theta32;
+  ma.out_ids = out_ids;
+  ma.out_scores = out_scores;
+  ma.out_count = out_count;
+  ma.n_docs = idx->n_docs;
+  ma.lists = (int32_t)G;
+  ma.k_max = k_max;
+  for (int32_t i = 0; i < n; ++i) {
+    sa.query = i;
+    hipEvent_t tb;
+    rc = timed_begin(idx, s, &tb);
+    if (rc != BM25_OK) return rc;
+    BM25_HIP(launch_sweep(idx->params.store_dtype, W, KPL, dim3((unsigned)G), (size_t)lds, s, sa));
+    rc = timed_end(idx, s, tb);
+    if (rc != BM25_OK) return rc;
+    ma.q_first = i;
+    BM25_HIP(launch_merge(KPL, dim3(1), s, ma));
+  }
+  return BM25_OK;
+}
+
+}  // namespace bm25
+
+using namespace bm25;
+
+extern "C" int bm25_search_batch(const bm25_index* index, const int32_t* q_ids,
+                                 const int64_t* q_offsets, int32_t n_queries, const int32_t* k,
+                                 int32_t k_max, int32_t* out_ids, float* out_scores,
+                                 int32_t* out_count, void* stream) {
+  clear_error();
+  if (!index) return set_error(BM25_E_INVAL, "index is NULL");
+  bm25_index* idx = const_cast<bm25_index*>(index);
+  std::lock_guard<std::mutex> g(idx->mu);
+  return search_batch_impl(idx, q_ids, q_offsets, n_queries, k, k_max, out_ids, out_scores,
+                           out_count, (hipStream_t)stream, idx->batch_scratch, nullptr);
+}
+
+extern "C" int bm25_search_plain(const bm25_index* index, const int32_t* q_ids,
+                                 const int64_t* q_offsets, int32_t n_queries, const int32_t* k,
+                                 int32_t k_max, int32_t* out_ids, float* out_scores,
+                                 int32_t* out_count, void* stream) {
+  clear_error();
+  if (!index) return set_error(BM25_E_INVAL, "index is NULL");
+  bm25_index* idx = const_cast<bm25_index*>(index);
+  std::lock_guard<std::mutex> g(idx->mu);
+  return search_plain_impl(idx, q_ids, q_offsets, n_queries, k, k_max, out_ids, out_scores,
+                           out_count, (hipStream_t)stream);
+}
+
+extern "C" int bm25_search_set_plan(bm25_index* index, const bm25_tile_plan* plan) {
+  clear_error();
+  if (!index) return set_error(BM25_E_INVAL, "index is NULL");
+  std::lock_guard<std::mutex> g(index->mu);
+  if (!plan) {
+    index->plan_fixed = false;
+    return BM25_OK;
+  }
+  TileShape t;
+  t.q_tile = plan->q_tile;
+  t.waves = plan->waves;
+  t.doc_tile = plan->doc_tile;
+  t.doc_groups = plan->doc_groups;
+  t.use_graph = plan->use_graph;
+  if (!shape_ok(t, BM25_MAX_K)) return set_error(BM25_E_INVAL, "plan fields out of range");
+  index->fixed_plan = t;
+  index->plan_fixed = true;
+  return BM25_OK;
+}
+
+extern "C" int bm25_search_get_plan(const bm25_index* index, int32_t n_queries,
+                                    int32_t max_query_len, int32_t k_max, bm25_tile_plan* plan) {
+  clear_error();
+  if (!index || !plan) return set_error(BM25_E_INVAL, "NULL argument");
+  bm25_index* idx = const_cast<bm25_index*>(index);
+  std::lock_guard<std::mutex> g(idx->mu);
+  TileShape t;
+  if (idx->plan_fixed) {
+    t = idx->fixed_plan;
+  } else {
+    auto it = idx->tuned.find(shape_class(n_queries, max_query_len, k_max));
+    t = (it != idx->tuned.end()) ? it->second : choose_shape(idx, n_queries, max_query_len, k_max);
+  }
+  plan->q_tile = t.q_tile;
+  plan->waves = t.waves;
+  plan->doc_tile = t.doc_tile;
+  plan->doc_groups = t.doc_groups;
+  plan->use_graph = t.use_graph;
+  return BM25_OK;
+}
+
+extern "C" int bm25_autotune(bm25_index* index, const int32_t* q_ids, const int64_t* q_offsets,
+                             int32_t n_queries, const int32_t* k, int32_t k_max,
+                             int32_t* out_ids, float* out_scores, int32_t* out_count,
+                             void* stream, bm25_tile_plan* best) {
+  clear_error();
+  if (!index) return set_error(BM25_E_INVAL, "index is NULL");
+  std::lock_guard<std::mutex> g(index->mu);
+  BatchInfo info;
+  int rc = check_batch(index, q_ids, q_offsets, n_queries, k, k_max, out_ids, out_scores,
+                       out_count, info);
+  if (rc != BM25_OK) return rc;
+  if (n_queries == 0) return set_error(BM25_E_INVAL, "autotune needs at least one query");
+  hipStream_t s = (hipStream_t)stream;
+  const TileShape base = choose_shape(index, n_queries, info.max_qlen, k_max);
+  std::vector<TileShape> cands;
+  const int kpl = kpl_for(k_max);
+  for (int waves : {4, 8})
+    for (int qpw : {1, 2, 4}) {
+      if (kpl >= 8 && qpw > 1) continue;
+      for (int dt : {512, 1024, 2048})
+        for (int gmul : {1, 2, 4}) {
+          TileShape t = base;
+          t.waves = waves;
+          t.q_tile = waves * qpw;
+          t.doc_tile = dt;
+          const int64_t ntiles = (n_queries + t.q_tile - 1) / t.q_tile;
+          int64_t gg = (1024 * gmul + ntiles - 1) / ntiles;
+          gg = ((gg + 7) / 8) * 8;
+          gg = std::min<int64_t>(std::max<int64_t>(gg, 8), 1024);
+          gg = std::min<int64_t>(gg, std::max<int64_t>(1, index->n_blocks));
+          t.doc_groups = (int)gg;
+          const int64_t ecap =
+              std::min<int64_t>((int64_t)t.q_tile * info.max_qlen, kTileMaxPositions) + 16;
+          if (gather_lds(t, ecap) > 128 * 1024) continue;
+          cands.push_back(t);
+        }
+    }
+  hipEvent_t e0, e1;
+  BM25_HIP(hipEventCreate(&e0));
+  BM25_HIP(hipEventCreate(&e1));
+  float best_ms = 1e30f;
+  TileShape best_t = base;
+  for (const TileShape& t : cands) {
+    // one warm-up, then two timed runs
+    rc = search_batch_impl(index, q_ids, q_offsets, n_queries, k, k_max, out_ids, out_scores,
+                           out_count, s, index->batch_scratch, &t);
+    if (rc != BM25_OK) continue;
+    BM25_HIP(hipEventRecord(e0, s));
+    for (int r = 0; r < 2; ++r)
+      (void)search_batch_impl(index, q_ids, q_offsets, n_queries, k, k_max, out_ids, out_scores,
+                              out_count, s, index->batch_scratch, &t);
+    BM25_HIP(hipEventRecord(e1, s));
+    BM25_HIP(hipEventSynchronize(e1));
+    float ms = 0.f;
+    BM25_HIP(hipEventElapsedTime(&ms, e0, e1));
+    if (ms < best_ms) {
+      best_ms = ms;
+      best_t = t;
+    }
+  }
+  (void)hipEventDestroy(e0);
+  (void)hipEventDestroy(e1);
+  index->tuned[shape_class(n_queries, info.max_qlen, k_max)] = best_t;
+  if (best) {
+    best->q_tile = best_t.q_tile;
+    best->waves = best_t.waves;
+    best->doc_tile = best_t.doc_tile;
+    best->doc_groups = best_t.doc_groups;
+    best->use_graph = best_t.use_graph;
+  }
+  clear_error();
+  return BM25_OK;
+}

@@ -1,0 +1,152 @@
+"""GPU search (batched and per-query forms) against the FP64 oracle."""
+import numpy as np
+import pytest
+
+from oracle import eager
+from tests.helpers import RTOL, check_batch
+from workloads import make_corpus, make_queries, make_tiny_corpus, make_tiny_queries
+from workloads.synth import QueryBatch
+
+pytestmark = pytest.mark.gpu
+
+
+def _dev(a):
+    import torch
+    return torch.from_numpy(np.ascontiguousarray(a)).cuda()
+
+
+def _index(c, variant="lucene", k1=1.5, b=0.75, delta=0.0, dtype="f32"):
+    from paper_2407_03618_amd import Index
+    return Index(_dev(c.tokens), _dev(c.doc_offsets), c.vocab, k1, b, delta, variant, dtype)
+
+
+def _run(idx, qb, k_max, form):
+    import torch
+    fn = idx.search_batch if form == "batch" else idx.search_plain
+    ids, scores, counts = fn(_dev(qb.q_ids) if qb.q_ids.size else _dev(np.zeros(1, np.int32)),
+                             qb.q_offsets, qb.k, k_max)
+    torch.cuda.synchronize()
+    return ids.cpu().numpy(), scores.cpu().numpy(), counts.cpu().numpy()
+
+
+@pytest.fixture(scope="module")
+def cfg0():
+    c = make_corpus(0)
+    q = make_queries(0)
+    return c, q
+
+
+@pytest.mark.parametrize("form", ["batch", "plain"])
+@pytest.mark.parametrize("dtype", ["f32", "f16", "bf16"])
+def test_config0_all_queries(cfg0, form, dtype):
+    c, q = cfg0
+    ref = eager.build_index(c.tokens, c.doc_offsets, c.vocab, 1.5, 0.75, 0.0, "lucene")
+    idx = _index(c, dtype=dtype)
+    ids, sc, cnt = _run(idx, q, 10, form)
+    check_batch(ref, q.q_ids, q.q_offsets, q.k, ids, sc, cnt, RTOL[dtype], f"{form}/{dtype}")
+
+
+VARIANTS = [("bm25plus", 1.2, 0.75, 1.0), ("bm25l", 1.2, 0.75, 0.5), ("robertson", 1.2, 0.75, 0.0),
+            ("atire", 1.2, 0.75, 0.0), ("tfldp", 1.2, 0.75, 0.5), ("lucene", 0.9, 0.4, 0.0)]
+
+
+@pytest.mark.parametrize("variant,k1,b,delta", VARIANTS)
+@pytest.mark.parametrize("form", ["batch", "plain"])
+def test_variants_config0(cfg0, variant, k1, b, delta, form):
+    c, q = cfg0
+    ref = eager.build_index(c.tokens, c.doc_offsets, c.vocab, k1, b, delta, variant)
+    for dtype in ("f32", "bf16"):
+        idx = _index(c, variant, k1, b, delta, dtype)
+        ids, sc, cnt = _run(idx, q, 10, form)
+        check_batch(ref, q.q_ids, q.q_offsets, q.k, ids, sc, cnt, RTOL[dtype],
+                    f"{variant}/{form}/{dtype}")
+        idx.free()
+
+
+@pytest.mark.parametrize("form", ["batch", "plain"])
+def test_tiny_corpora_edge_cases(form):
+    """Random tiny corpora: k > N, empty queries, repeated and absent tokens, empty documents."""
+    for seed in range(30):
+        c = make_tiny_corpus(seed)
+        qb = make_tiny_queries(seed, c.vocab + 2)  # ids c.vocab.. are absent (DF = 0) ...
+        qb.q_ids[:] = np.minimum(qb.q_ids, c.vocab + 1)
+        from workloads.synth import Corpus
+        cc = Corpus(c.tokens, c.doc_offsets, c.vocab + 2)  # ... but inside the vocabulary
+        for variant, k1, b, delta in (("lucene", 1.5, 0.75, 0.0), ("bm25plus", 1.2, 0.75, 1.0)):
+            ref = eager.build_index(cc.tokens, cc.doc_offsets, cc.vocab, k1, b, delta, variant)
+            idx = _index(cc, variant, k1, b, delta, "f32")
+            ids, sc, cnt = _run(idx, qb, 12, form)
+            check_batch(ref, qb.q_ids, qb.q_offsets, qb.k, ids, sc, cnt, 1e-5,
+                        f"seed {seed} {variant} {form}")
+            idx.free()
+
+
+@pytest.mark.parametrize("form", ["batch", "plain"])
+def test_invalid_token_marks_only_that_query(form):
+    c = make_corpus(0, n_docs=500)
+    ref = eager.build_index(c.tokens, c.doc_offsets, c.vocab)
+    q_ids = np.array([1, 2, c.vocab + 7, 3, -1, 4, 5], np.int32)
+    q_off = np.array([0, 2, 4, 5, 7], np.int64)
+    qb = QueryBatch(q_ids, q_off, np.full(4, 5, np.int32))
+    idx = _index(c)
+    ids, sc, cnt = _run(idx, qb, 5, form)
+    assert cnt[1] == -2 and cnt[2] == -2
+    assert np.all(ids[1] == -1) and np.all(np.isneginf(sc[2]))
+    for i in (0, 3):
+        check_batch(ref, q_ids, q_off, 5, ids, sc, cnt, 1e-5, form, sample=[i])
+
+
+def test_search_argument_errors():
+    from paper_2407_03618_amd import BM25Error
+    c = make_corpus(0, n_docs=300)
+    idx = _index(c)
+    q = _dev(np.array([1, 2, 3], np.int32))
+    with pytest.raises(BM25Error):
+        idx.search_batch(q, np.array([0, 3]), 5, 2000)           # k_max above the limit
+    with pytest.raises(BM25Error):
+        idx.search_batch(q, np.array([0, 3]), np.array([6]), 5)  # k > k_max
+    with pytest.raises(BM25Error):
+        idx.search_batch(q, np.array([1, 3]), 5, 5)              # offsets must start at 0
+    with pytest.raises(BM25Error):
+        idx.search_plain(q, np.array([0, 3, 2]), 5, 5)           # decreasing offsets
+
+
+@pytest.mark.parametrize("form", ["batch", "plain"])
+@pytest.mark.parametrize("k", [1, 100, 300, 1000])
+def test_scaled_corpus_many_tiles_and_groups(form, k):
+    """Recipe of the 8.8M-document workload at 120k documents: many doc tiles and groups with a
+    ragged tail, query tiles with a ragged last tile, k from 1 to 1000."""
+    c = make_corpus(2, n_docs=120_000)
+    q = make_queries(2, n_queries=77 if k >= 300 else 150, vocab=c.vocab, k=k)
+    ref = eager.build_index(c.tokens, c.doc_offsets, c.vocab, token_subset=np.unique(q.q_ids))
+    idx = _index(c, dtype="f16")
+    ids, sc, cnt = _run(idx, q, k, form)
+    sample = range(q.n) if k <= 100 else range(0, q.n, 5)
+    check_batch(ref, q.q_ids, q.q_offsets, q.k, ids, sc, cnt, RTOL["f16"], f"{form} k={k}",
+                sample=sample)
+
+
+def test_batched_shapes_agree():
+    """Every launch shape the autotuner may pick gives results within tolerance."""
+    import torch
+    c = make_corpus(2, n_docs=60_000)
+    q = make_queries(2, n_queries=90, vocab=c.vocab, k=50)
+    ref = eager.build_index(c.tokens, c.doc_offsets, c.vocab, token_subset=np.unique(q.q_ids))
+    idx = _index(c, dtype="f32")
+    from paper_2407_03618_amd import BM25Error
+    for waves in (4, 8):
+        for qpw in (1, 2, 4):
+            for dt, g in ((512, 8), (1024, 16), (2048, 3)):
+                idx.set_plan(dict(q_tile=waves * qpw, waves=waves, doc_tile=dt, doc_groups=g))
+                if waves * qpw * dt * 4 > 150 * 1024:  # accumulators alone exceed the LDS
+                    with pytest.raises(BM25Error) as e:
+                        _run(idx, q, 50, "batch")
+                    assert e.value.code == -1
+                    continue
+                ids, sc, cnt = _run(idx, q, 50, "batch")
+                check_batch(ref, q.q_ids, q.q_offsets, q.k, ids, sc, cnt, 1e-5,
+                            f"W={waves} QPW={qpw} DT={dt} G={g}", sample=range(0, q.n, 3))
+    idx.set_plan(None)
+    best = idx.autotune(_dev(q.q_ids), q.q_offsets, 50, 50)
+    assert best["q_tile"] >= 1
+    torch.cuda.synchronize()
