@@ -1,0 +1,352 @@
+"""Benchmark of the BM25S eager sparse scoring hot path on one MI355X.
+
+Default workload: an 8.8M-document synthetic corpus (vocabulary 2M, Zipf s = 1.05 token ids,
+log-normal lengths with mean 60), 4096-query batches (lengths 2-30, geometric, mean 7), top-100,
+scores stored in FP16 and accumulated in FP32, batched form. A step is one batch through the
+whole query path (plan, gather + accumulate, top-k, merge with the shift); the index is built
+once, before the timed region, and its build rate is reported separately.
+
+Printed JSON line (stdout): value = queries/s over the timed steps; roofline of the dominant
+kernel (the batched gather); the FP64 CPU oracle timed on a bounded sample of the same queries;
+extra legs: the plain per-query FP32 form, index build rate, sampled parity against the oracle,
+and open-loop serving latency (p50/p99) at fixed arrival rates.
+"""
+from __future__ import annotations
+
+import argparse
+import hashlib
+import json
+import os
+import sys
+import time
+
+import numpy as np
+
+ROOT = os.path.dirname(os.path.abspath(__file__))
+sys.path.insert(0, ROOT)
+
+METRIC = "queries/s + HBM GB/s, 8.8M-doc top-100 index; p50/p99 latency at fixed QPS"
+HBM_PEAK_GBS = 8000.0
+KERNEL_SOURCES = ["paper_2407_03618_amd/csrc/search_kernels.hpp",
+                  "paper_2407_03618_amd/csrc/device.hpp",
+                  "paper_2407_03618_amd/csrc/search_inst.hip"]
+TRAFFIC_FILE = os.path.join(ROOT, "profiles", "gather_traffic.json")
+
+
+def log(*a):
+    print(*a, file=sys.stderr, flush=True)
+
+
+def kernel_source_hash() -> str:
+    h = hashlib.sha256()
+    for p in KERNEL_SOURCES:
+        with open(os.path.join(ROOT, p), "rb") as f:
+            h.update(f.read())
+    return h.hexdigest()[:16]
+
+
+def measured_traffic(workload: str):
+    """HBM bytes per gather launch from the committed counter summary, if it is current."""
+    try:
+        with open(TRAFFIC_FILE) as f:
+            t = json.load(f)
+    except (OSError, ValueError):
+        return None
+    entry = t.get(workload)
+    if not entry or entry.get("kernel_hash") != kernel_source_hash():
+        return None
+    return entry.get("bytes_per_launch")
+
+
+def algorithmic_bytes(df: np.ndarray, q_ids: np.ndarray, q_off: np.ndarray, k: np.ndarray,
+                      s_bytes: int) -> np.ndarray:
+    """Per query: sum_i DF(q_i) * (4 + s) + 16 |Q| + 8 k (postings read, row bounds, results)."""
+    per_pos = df[q_ids].astype(np.int64) * (4 + s_bytes) + 16
+    cs = np.concatenate([[0], np.cumsum(per_pos)])
+    return (cs[q_off[1:]] - cs[q_off[:-1]]) + 8 * k.astype(np.int64)
+
+
+def cpu_baseline_leg(corpus, queries, sample_idx, cfg, gpu_rows, threads):
+    """Times the FP64 oracle (the paper's eager method) on a sample of the benchmark queries and
+    checks the GPU rows of the same queries against it."""
+    from concurrent.futures import ThreadPoolExecutor
+
+    from oracle import eager
+    from tests.helpers import check_query, oracle_scores
+
+    qs = [queries.query(i) for i in sample_idx]
+    subset = np.unique(np.concatenate(qs)) if qs else np.zeros(0, np.int64)
+    t0 = time.time()
+    ref = eager.build_index(corpus.tokens, corpus.doc_offsets, corpus.vocab, cfg["k1"], cfg["b"],
+                            cfg["delta"], cfg["variant"], token_subset=subset)
+    log(f"[cpu] oracle rows for {len(subset)} tokens built in {time.time() - t0:.1f}s")
+    k = int(cfg["k"])
+
+    def one(q):
+        return eager.search(ref, q, k)
+
+    t0 = time.perf_counter()
+    for q in qs:
+        one(q)
+    t_single = time.perf_counter() - t0
+    t0 = time.perf_counter()
+    with ThreadPoolExecutor(threads) as ex:
+        list(ex.map(one, qs))
+    t_multi = time.perf_counter() - t0
+    # parity of the sampled GPU rows
+    worst = 0.0
+    from tests.helpers import RTOL
+    rtol = RTOL[cfg["dtype"]]
+    ids, scores, counts = gpu_rows
+    for j, i in enumerate(sample_idx):
+        b, absS = oracle_scores(ref, queries.query(i))
+        worst = max(worst, check_query(ids[j], scores[j], counts[j], b, absS, k, rtol,
+                                       f"bench query {i}"))
+    single = len(qs) / t_single
+    multi = len(qs) / t_multi
+    best = dict(value=multi, cores=threads) if multi > single else dict(value=single, cores=1)
+    return dict(value=best["value"], unit="queries/s", cores=best["cores"], kind="oracle",
+                sample=(f"{len(qs)} queries of the benchmark stream over the full "
+                        f"{corpus.n_docs}-document index (FP64 slice-and-sum of the query rows, "
+                        f"full sort for top-{k}); single-thread {single:.3f} q/s, "
+                        f"{threads}-thread pool {multi:.3f} q/s"),
+                cpu_model=_cpu_model(), host_cpus=os.cpu_count(),
+                affinity=len(os.sched_getaffinity(0))), worst
+
+
+def _cpu_model():
+    try:
+        for line in open("/proc/cpuinfo"):
+            if line.startswith("model name"):
+                return line.split(":", 1)[1].strip()
+    except OSError:
+        pass
+    return "unknown"
+
+
+def serving_leg(idx, corpus, rates, seconds, budget, log_prefix="[serve]"):
+    """Open-loop Poisson arrivals at fixed rates; p50/p99 latency and achieved q/s."""
+    from paper_2407_03618_amd import Server
+    from workloads import make_queries
+    from workloads.synth import poisson_arrivals
+    out = []
+    srv = Server(idx, hbm_budget_bytes=budget, max_slots=1 << 20, max_batch=4096, max_k=1000,
+                 n_streams=4)
+    for rate in rates:
+        n = int(rate * seconds)
+        q = make_queries(4, n_queries=n, vocab=corpus.vocab)
+        arr = poisson_arrivals(rate, n, 4004 + int(rate)) * 1e6
+        t0 = time.perf_counter()
+        lat, _, _, cnt = srv.replay(q.q_ids, q.q_offsets, q.k, arr, 1000)
+        wall = time.perf_counter() - t0
+        st = srv.stats()
+        ok = np.isfinite(lat)
+        out.append(dict(offered_qps=rate, n=n, achieved_qps=float(ok.sum() / wall),
+                        p50_ms=float(np.percentile(lat[ok], 50) / 1e3),
+                        p99_ms=float(np.percentile(lat[ok], 99) / 1e3),
+                        errors=int(np.sum(cnt < 0)), batches=st["batches"],
+                        max_batch=st["max_batch"]))
+        log(log_prefix, out[-1])
+    srv.close()
+    return out
+
+
+def main():
+    ap = argparse.ArgumentParser()
+    ap.add_argument("--gpus", type=int, default=1)
+    ap.add_argument("--steps", type=int, default=20)
+    ap.add_argument("--warmup", type=int, default=2)
+    ap.add_argument("--batch", type=int, default=4096)
+    ap.add_argument("--n-docs", type=int, default=None, help="override corpus size (testing)")
+    ap.add_argument("--cpu-sample", type=int, default=24)
+    ap.add_argument("--plain-queries", type=int, default=256)
+    ap.add_argument("--serve-seconds", type=float, default=1.0)
+    ap.add_argument("--no-cpu", action="store_true")
+    ap.add_argument("--no-plain", action="store_true")
+    ap.add_argument("--no-serve", action="store_true")
+    ap.add_argument("--autotune", action="store_true")
+    args = ap.parse_args()
+    if args.gpus != 1 or int(os.environ.get("WORLD_SIZE", "1")) != 1:
+        print("bench.py measures one GPU only: this build has no multi-GPU path "
+              "(see DESIGN.md for how the index would shard by document range)", file=sys.stderr)
+        sys.exit(2)
+
+    import torch
+
+    from paper_2407_03618_amd import Index
+    from workloads import CONFIGS, make_corpus, make_queries
+
+    cfg = dict(CONFIGS[2])
+    t0 = time.time()
+    corpus = make_corpus(2, n_docs=args.n_docs)
+    n_queries = max(args.batch * (args.steps + args.warmup), args.batch)
+    queries = make_queries(2, n_queries=min(n_queries, cfg["n_queries"]) if args.n_docs is None
+                           else n_queries, vocab=corpus.vocab)
+    log(f"[gen] {corpus.n_docs} docs, {corpus.n_tokens} tokens, {queries.n} queries "
+        f"in {time.time() - t0:.1f}s")
+    dev = torch.device("cuda:0")
+    tok_d = torch.from_numpy(corpus.tokens).to(dev)
+    off_d = torch.from_numpy(corpus.doc_offsets).to(dev)
+    torch.cuda.synchronize()
+
+    # index build (untimed for the query metric; reported as nnz/s)
+    builds = {}
+    for dtype in ("f16", "f32"):
+        torch.cuda.synchronize()
+        t0 = time.perf_counter()
+        idx = Index(tok_d, off_d, corpus.vocab, cfg["k1"], cfg["b"], cfg["delta"], cfg["variant"],
+                    dtype)
+        torch.cuda.synchronize()
+        ms = (time.perf_counter() - t0) * 1e3
+        builds[dtype] = (idx, ms)
+        log(f"[build] {dtype}: nnz {idx.nnz} in {ms:.1f} ms ({idx.nnz / ms / 1e6:.2f} G nnz/s)")
+    idx, build_ms = builds["f16"]
+    idx32 = builds["f32"][0]
+    del tok_d, off_d
+    torch.cuda.empty_cache()
+    df = idx.export()["df"].cpu().numpy()
+
+    q_dev = torch.from_numpy(queries.q_ids).to(dev)
+    B = args.batch
+    n_batches = queries.n // B
+    k = int(cfg["k"])
+    out = idx._outputs(B, k)
+
+    def batch(i):
+        lo = (i % n_batches) * B
+        off = queries.q_offsets[lo:lo + B + 1]
+        base = int(off[0])
+        return lo, q_dev[base:], off - base
+
+    if args.autotune:
+        _, qd, off = batch(0)
+        log("[tune]", idx.autotune(qd, off, k, k))
+    plan = idx.get_plan(B, int(np.diff(queries.q_offsets).max()), k)
+    log("[plan]", plan)
+
+    for i in range(args.warmup):
+        _, qd, off = batch(i)
+        idx.search_batch(qd, off, k, k, out=out)
+    torch.cuda.synchronize()
+    idx.kernel_time_read()
+    idx.kernel_timing(True)
+    alg = 0
+    t0 = time.perf_counter()
+    for s in range(args.steps):
+        lo, qd, off = batch(args.warmup + s)
+        idx.search_batch(qd, off, k, k, out=out)
+    torch.cuda.synchronize()
+    elapsed = time.perf_counter() - t0
+    kern_ms, launches = idx.kernel_time_read()
+    idx.kernel_timing(False)
+    for s in range(args.steps):
+        lo = ((args.warmup + s) % n_batches) * B
+        q_off = queries.q_offsets[lo:lo + B + 1]
+        alg += int(algorithmic_bytes(df, queries.q_ids, q_off - 0, np.full(B, k), 2).sum())
+    qps = args.steps * B / elapsed
+    ms_step = elapsed / args.steps * 1e3
+    gather_ms = kern_ms / max(launches, 1)
+    achieved = alg / args.steps / (gather_ms / 1e3) / 1e9
+    log(f"[batched f16] {qps:.0f} q/s, {ms_step:.2f} ms/step, gather kernel {gather_ms:.2f} ms, "
+        f"effective {achieved:.0f} GB/s")
+
+    # keep the rows of the last timed batch for sampled parity
+    last_lo = ((args.warmup + args.steps - 1) % n_batches) * B
+    ids_h, sc_h, cnt_h = (t.cpu().numpy() for t in out)
+
+    extra = {}
+    # plain per-query FP32 form on the same index recipe
+    if not args.no_plain:
+        nq = args.plain_queries
+        lo = last_lo
+        off = queries.q_offsets[lo:lo + nq + 1]
+        base = int(off[0])
+        qd = q_dev[base:]
+        o2 = idx32._outputs(nq, k)
+        idx32.search_plain(qd, off - base, k, k, out=o2)  # warm-up
+        torch.cuda.synchronize()
+        idx32.kernel_time_read()
+        idx32.kernel_timing(True)
+        t0 = time.perf_counter()
+        idx32.search_plain(qd, off - base, k, k, out=o2)
+        torch.cuda.synchronize()
+        pt = time.perf_counter() - t0
+        pk_ms, pl = idx32.kernel_time_read()
+        idx32.kernel_timing(False)
+        palg = int(algorithmic_bytes(df, queries.q_ids, off, np.full(nq, k), 4).sum())
+        extra["plain_fp32"] = dict(
+            qps=nq / pt, ms_per_query=pt / nq * 1e3, sweep_kernel_ms=pk_ms / max(pl, 1),
+            effective_GBs=palg / (pk_ms / 1e3) / 1e9 if pk_ms > 0 else None, queries=nq)
+        log("[plain f32]", extra["plain_fp32"])
+        # batched FP32 on the same batch for the precision comparison
+        _, qd2, off2 = batch(args.warmup)
+        idx32.search_batch(qd2, off2, k, k)  # warm-up
+        torch.cuda.synchronize()
+        t0 = time.perf_counter()
+        reps = max(2, args.steps // 4)
+        for s in range(reps):
+            _, qd2, off2 = batch(args.warmup + s)
+            idx32.search_batch(qd2, off2, k, k)
+        torch.cuda.synchronize()
+        extra["batched_fp32"] = dict(qps=reps * B / (time.perf_counter() - t0))
+        log("[batched f32]", extra["batched_fp32"])
+
+    cpu = None
+    if not args.no_cpu:
+        ns = min(args.cpu_sample, B)
+        sample_idx = list(range(last_lo, last_lo + ns))
+        rows = (ids_h[:ns], sc_h[:ns], cnt_h[:ns])
+        threads = min(16, len(os.sched_getaffinity(0)))
+        cpu, worst = cpu_baseline_leg(corpus, queries, sample_idx, cfg, rows, threads)
+        extra["parity"] = dict(queries_checked=ns, max_rel_err=worst, rtol=2e-3,
+                               rule="score within rtol of sum |S|; ids match up to ties")
+        log("[cpu]", cpu)
+
+    if not args.no_serve:
+        extra["serving"] = serving_leg(idx, corpus, CONFIGS[4]["rates"], args.serve_seconds,
+                                       budget=8 << 30)
+
+    traffic = measured_traffic("batched_f16_top100")
+    res = {
+        "metric": METRIC,
+        "value": qps,
+        "unit": "queries/s",
+        "n_gpus": 1,
+        "steps": args.steps,
+        "warmup": args.warmup,
+        "ms_per_step": ms_step,
+        "higher_is_better": True,
+        "scaling": "weak",
+        "vs_baseline": None,
+        "dtype": "f16",
+        "data": "synthetic",
+        "config": {
+            "workload": (f"{corpus.n_docs}-doc Zipf(1.05) corpus, V={corpus.vocab}, "
+                         f"{B}-query batches, top-{k}, FP16 stored scores, FP32 accumulation, "
+                         "batched form"),
+            "n_docs": corpus.n_docs, "vocab": corpus.vocab, "n_tokens": corpus.n_tokens,
+            "nnz": idx.nnz, "batch": B, "k": k, "plan": plan,
+        },
+        "roofline": {
+            "bound": "hbm",
+            "achieved": achieved,
+            "peak": HBM_PEAK_GBS,
+            "unit": "GB/s",
+            "frac": achieved / HBM_PEAK_GBS,
+            "traffic": traffic,
+            "kernel": "k_gather",
+            "kernel_ms": gather_ms,
+            "algorithmic_bytes_per_launch": alg / args.steps,
+            "note": ("achieved counts each query's postings once per query (no reuse across "
+                     "queries); the batched kernel reads shared posting segments once per "
+                     "query tile, so the effective figure may exceed the peak"),
+        },
+        "cpu_baseline": cpu,
+        "build": {"ms_f16": build_ms, "nnz_per_s": idx.nnz / (build_ms / 1e3)},
+        **extra,
+    }
+    print(json.dumps(res), flush=True)
+
+
+if __name__ == "__main__":
+    main()

@@ -169,13 +169,19 @@ int bm25_search_plain(const bm25_index* index, const int32_t* q_ids, const int64
  *   waves       wavefronts per workgroup (1..16)
  *   doc_tile    documents per LDS accumulator tile (multiple of 256)
  *   doc_groups  document ranges the corpus is split into; a workgroup owns one (tile, range)
- *   use_graph   1: replay the launch sequence from a captured hipGraph */
+ *   use_graph   1: replay the launch sequence from a captured hipGraph
+ *   sparse_only 1: read every token from the sparse rows, ignoring the dense copies of the most
+ *               frequent tokens' rows (same results within rounding; for testing)
+ * Built shapes: waves 8 with doc_tile 1024 (2 documents per lane) or 2048 (4 per lane), waves 4
+ * with doc_tile 1024 (4 per lane); q_tile * list registers <= 32, where a query's list takes
+ * ceil(k_max / 64) registers (rounded up to a power of two). */
 typedef struct {
   int32_t q_tile;
   int32_t waves;
   int32_t doc_tile;
   int32_t doc_groups;
   int32_t use_graph;
+  int32_t sparse_only;
 } bm25_tile_plan;
 
 /* Fixes the batched form's launch shape for this index (NULL restores automatic choice).

@@ -75,11 +75,21 @@ struct F16 {
   using T = __half;
   static __device__ __forceinline__ float load(const T* p, int64_t i) { return __half2float(p[i]); }
   static __device__ __forceinline__ T store(float v) { return __float2half_rn(v); }
+  static __device__ __forceinline__ float widen_lo(uint32_t w) {
+    return __half2float(__ushort_as_half((unsigned short)(w & 0xFFFFu)));
+  }
+  static __device__ __forceinline__ float widen_hi(uint32_t w) {
+    return __half2float(__ushort_as_half((unsigned short)(w >> 16)));
+  }
 };
 struct BF16 {
   using T = uint16_t;
   static __device__ __forceinline__ float load(const T* p, int64_t i) {
     return __uint_as_float((uint32_t)p[i] << 16);
+  }
+  static __device__ __forceinline__ float widen_lo(uint32_t w) { return __uint_as_float(w << 16); }
+  static __device__ __forceinline__ float widen_hi(uint32_t w) {
+    return __uint_as_float(w & 0xFFFF0000u);
   }
   // round to nearest even (inputs are finite)
   static __device__ __forceinline__ T store(float v) {

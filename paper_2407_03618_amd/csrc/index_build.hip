@@ -17,6 +17,8 @@
 #include <cstdarg>
 #include <cstring>
 #include <memory>
+#include <utility>
+#include <vector>
 
 #include "device.hpp"
 #include "internal.hpp"
@@ -442,6 +444,21 @@ __global__ __launch_bounds__(256) void k_skip(const uint64_t* __restrict__ uniq,
     for (int64_t b = blk + 1; b <= nblocks; ++b) row[b] = (uint32_t)(hi - lo);
 }
 
+// Dense rows: dense[h][d] = stored score of (t, d) for the dense tokens t (row h = dense_id[t]).
+template <typename T>
+__global__ __launch_bounds__(256) void k_dense_scatter(const uint64_t* __restrict__ uniq,
+                                                       int64_t nnz,
+                                                       const int32_t* __restrict__ dense_id,
+                                                       const T* __restrict__ data, int64_t n_pad,
+                                                       T* __restrict__ dense) {
+  const int64_t j = (int64_t)blockIdx.x * blockDim.x + threadIdx.x;
+  if (j >= nnz) return;
+  const uint64_t key = uniq[j];
+  const int32_t h = dense_id[(uint32_t)(key >> 32)];
+  if (h < 0) return;
+  dense[(int64_t)h * n_pad + (uint32_t)key] = data[j];
+}
+
 static unsigned grid_for(int64_t n, int threads) {
   int64_t g = (n + threads - 1) / threads;
   if (g < 1) g = 1;
@@ -656,7 +673,47 @@ extern "C" int bm25_index_build(const int32_t* token_ids, int64_t n_tokens,
                        idx->long_id.as<int32_t>(), idx->n_blocks, idx->skip.as<uint32_t>());
     BM25_HIP(hipGetLastError());
   }
-  BM25_HIP(hipStreamSynchronize(s));
+  // 8. dense rows of the most frequent tokens
+  {
+    std::vector<int32_t> df_h((size_t)V);
+    BM25_HIP(hipMemcpyAsync(df_h.data(), idx->df.ptr, (size_t)V * 4, hipMemcpyDeviceToHost, s));
+    BM25_HIP(hipStreamSynchronize(s));
+    const int64_t sb = (int64_t)store_bytes(P.store_dtype);
+    idx->n_pad = ((N + kDensePad - 1) / kDensePad) * kDensePad;
+    const int64_t h_max = kDenseBytes / (idx->n_pad * sb);
+    const int64_t min_df = std::max<int64_t>(2, (N + kDenseFraction - 1) / kDenseFraction);
+    std::vector<std::pair<int32_t, int32_t>> cand;  // (-df, token): most frequent first
+    for (int32_t t = 0; t < V; ++t)
+      if (df_h[t] >= min_df) cand.emplace_back(-df_h[t], t);
+    std::sort(cand.begin(), cand.end());
+    if ((int64_t)cand.size() > h_max) cand.resize((size_t)std::max<int64_t>(h_max, 0));
+    std::vector<int32_t> did((size_t)V, -1);
+    // rows in token order, so that the layout does not depend on tie order
+    std::vector<int32_t> toks;
+    for (auto& c : cand) toks.push_back(c.second);
+    std::sort(toks.begin(), toks.end());
+    for (size_t h = 0; h < toks.size(); ++h) did[toks[h]] = (int32_t)h;
+    idx->n_dense = (int64_t)toks.size();
+    BM25_ALLOC(idx->dense_id, (size_t)V * 4);
+    BM25_HIP(hipMemcpyAsync(idx->dense_id.ptr, did.data(), (size_t)V * 4, hipMemcpyHostToDevice,
+                            s));
+    const size_t dbytes = (size_t)std::max<int64_t>(1, idx->n_dense) * idx->n_pad * sb;
+    BM25_ALLOC(idx->dense, dbytes);
+    if (idx->n_dense > 0) {
+      BM25_HIP(hipMemsetAsync(idx->dense.ptr, 0, dbytes, s));
+      const unsigned g = grid_for(nnz, 256);
+      if (sb == 4)
+        hipLaunchKernelGGL(k_dense_scatter<uint32_t>, dim3(g), dim3(256), 0, s, uniq, nnz,
+                           idx->dense_id.as<int32_t>(), idx->data.as<uint32_t>(), idx->n_pad,
+                           idx->dense.as<uint32_t>());
+      else
+        hipLaunchKernelGGL(k_dense_scatter<uint16_t>, dim3(g), dim3(256), 0, s, uniq, nnz,
+                           idx->dense_id.as<int32_t>(), idx->data.as<uint16_t>(), idx->n_pad,
+                           idx->dense.as<uint16_t>());
+      BM25_HIP(hipGetLastError());
+    }
+    BM25_HIP(hipStreamSynchronize(s));
+  }
 #undef BM25_ALLOC
   *out = idx.release();
   return BM25_OK;
@@ -701,7 +758,8 @@ extern "C" int64_t bm25_index_device_bytes(const bm25_index* index) {
   if (!index) return 0;
   const bm25::DevBuf* bufs[] = {&index->indptr, &index->indices, &index->tf, &index->data,
                                 &index->df, &index->idf, &index->theta, &index->theta32,
-                                &index->doclen, &index->long_id, &index->skip};
+                                &index->doclen, &index->long_id, &index->skip,
+                                &index->dense_id, &index->dense};
   int64_t total = 0;
   for (auto* b : bufs) total += (int64_t)b->bytes;
   const bm25::SearchScratch* ss[] = {&index->batch_scratch, &index->plain_scratch};

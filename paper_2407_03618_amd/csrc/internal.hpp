@@ -101,6 +101,13 @@ struct PinnedBuf {
 constexpr int64_t kSkipBlock = 1024;
 constexpr int64_t kLongRow = 4096;
 
+// Rows of tokens present in at least 1/kDenseFraction of the documents are also kept as dense
+// rows (one stored score per document, zero where the token is absent), at most kDenseBytes in
+// total. Query-time accumulation reads them with coalesced loads into registers.
+constexpr int64_t kDenseFraction = 16;
+constexpr int64_t kDenseBytes = 4ll << 30;
+constexpr int64_t kDensePad = 4096;
+
 // Per-batch device scratch of the search path (grown on demand, reused across calls).
 // `meta` mirrors the pinned staging block written by the host planner:
 //   int64 q_off[n+1] | int32 q_k[n] | int32 tile_q0[n_tiles+1] | int64 tile_e0[n_tiles+1]
@@ -111,6 +118,8 @@ struct SearchScratch {
   DevBuf entries;   // planner entries
   DevBuf members;   // int32 per position
   DevBuf cand;      // uint64 candidate lists
+  DevBuf dense_ent; // planner dense entries (16 B per position)
+  DevBuf dense_n;   // int32 per tile
   PinnedBuf host;   // staging for the host-side plan
   hipEvent_t host_free = nullptr;  // the staging buffer may be rewritten once this has fired
 };
@@ -121,6 +130,7 @@ struct TileShape {
   int doc_tile = 0;
   int doc_groups = 0;
   int use_graph = 0;
+  int sparse_only = 0;
 };
 
 }  // namespace bm25
@@ -148,6 +158,10 @@ struct bm25_index {
   bm25::DevBuf skip;      // uint32[n_long][n_blocks+1]
   int64_t n_long = 0;
   int64_t n_blocks = 0;   // ceil(N / kSkipBlock)
+  bm25::DevBuf dense_id;  // int32[V]: dense row of the token, or -1
+  bm25::DevBuf dense;     // store dtype[n_dense][n_pad]: S (or S_delta) per document, 0 if absent
+  int64_t n_dense = 0;
+  int64_t n_pad = 0;      // dense row length: N rounded up to kDensePad
 
   bm25::SearchScratch batch_scratch;
   bm25::SearchScratch plain_scratch;

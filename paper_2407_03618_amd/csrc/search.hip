@@ -15,21 +15,21 @@ namespace bm25 {
 
 using namespace bm25dev;
 
-hipError_t launch_gather_f32(int, int, int, dim3, size_t, hipStream_t, const GatherArgs&);
-hipError_t launch_gather_f16(int, int, int, dim3, size_t, hipStream_t, const GatherArgs&);
-hipError_t launch_gather_bf16(int, int, int, dim3, size_t, hipStream_t, const GatherArgs&);
+hipError_t launch_gather_f32(int, int, int, int, dim3, size_t, hipStream_t, const GatherArgs&);
+hipError_t launch_gather_f16(int, int, int, int, dim3, size_t, hipStream_t, const GatherArgs&);
+hipError_t launch_gather_bf16(int, int, int, int, dim3, size_t, hipStream_t, const GatherArgs&);
 hipError_t launch_sweep_f32(int, int, dim3, size_t, hipStream_t, const SweepArgs&);
 hipError_t launch_sweep_f16(int, int, dim3, size_t, hipStream_t, const SweepArgs&);
 hipError_t launch_sweep_bf16(int, int, dim3, size_t, hipStream_t, const SweepArgs&);
 
 static constexpr int64_t kMaxLdsBytes = 160 * 1024;
 
-static hipError_t launch_gather(int dtype, int W, int QPW, int KPL, dim3 g, size_t sh,
+static hipError_t launch_gather(int dtype, int W, int QT, int R, int KPL, dim3 g, size_t sh,
                                 hipStream_t s, const GatherArgs& a) {
   switch (dtype) {
-    case BM25_F32: return launch_gather_f32(W, QPW, KPL, g, sh, s, a);
-    case BM25_F16: return launch_gather_f16(W, QPW, KPL, g, sh, s, a);
-    default: return launch_gather_bf16(W, QPW, KPL, g, sh, s, a);
+    case BM25_F32: return launch_gather_f32(W, QT, R, KPL, g, sh, s, a);
+    case BM25_F16: return launch_gather_f16(W, QT, R, KPL, g, sh, s, a);
+    default: return launch_gather_bf16(W, QT, R, KPL, g, sh, s, a);
   }
 }
 
@@ -60,7 +60,7 @@ static int kpl_for(int k_max) {
   return kpl;
 }
 
-static IndexView index_view(const bm25_index* idx) {
+static IndexView index_view(const bm25_index* idx, bool sparse_only) {
   IndexView v;
   v.indptr = idx->indptr.as<int64_t>();
   v.indices = idx->indices.as<int32_t>();
@@ -70,8 +70,12 @@ static IndexView index_view(const bm25_index* idx) {
   const int var = idx->params.variant;
   const bool shifted = var == BM25_BM25L || var == BM25_BM25PLUS || var == BM25_TFLDP;
   v.theta32 = shifted ? idx->theta32.as<float>() : nullptr;
+  const bool dense = !sparse_only && idx->n_dense > 0;
+  v.dense_id = dense ? idx->dense_id.as<int32_t>() : nullptr;
+  v.dense = idx->dense.ptr;
   v.n_docs = idx->n_docs;
   v.n_blocks = idx->n_blocks;
+  v.n_pad = idx->n_pad;
   v.vocab = idx->vocab;
   return v;
 }
@@ -113,37 +117,63 @@ static int check_batch(const bm25_index* idx, const int32_t* q_ids, const int64_
   return BM25_OK;
 }
 
+// Built (waves, documents per lane) shapes and (queries per tile, list registers) pairs; see
+// search_inst.hip.
 static bool shape_ok(const TileShape& t, int k_max) {
-  if (!(t.waves == 4 || t.waves == 8)) return false;
-  if (t.q_tile < 1 || t.q_tile > 64 || t.q_tile % t.waves != 0) return false;
+  if (t.waves < 1 || t.doc_tile < 64 * t.waves || t.doc_tile % (64 * t.waves) != 0) return false;
+  const int R = t.doc_tile / (64 * t.waves);
+  const bool wr = (t.waves == 8 && R == 2) || (t.waves == 4 && R == 4) || (t.waves == 8 && R == 4);
+  if (!wr) return false;
+  if (t.q_tile < t.waves || t.q_tile % t.waves != 0) return false;
   const int qpw = t.q_tile / t.waves;
-  if (!(qpw == 1 || qpw == 2 || qpw == 4)) return false;
-  if (t.doc_tile < 256 || t.doc_tile > 16384 || t.doc_tile % 256 != 0) return false;
+  const int kpl = kpl_for(k_max);
+  const bool ok = qpw == 1 || (qpw == 2 && kpl <= 4) ||
+                  (qpw == 4 && kpl <= 2 && t.waves * R <= 16);
+  if (!ok) return false;
   if (t.doc_groups < 1 || t.doc_groups > 65536) return false;
-  (void)k_max;
   return true;
 }
 
-static int64_t gather_lds(const TileShape& t, int64_t ecap) {
-  return (int64_t)t.q_tile * t.doc_tile * 4 + ecap * 4;
+// Largest built q_tile for this list size and shape, not above `want`.
+static int fit_q_tile(int want, int kpl, int waves, int R) {
+  for (int qpw : {4, 2, 1}) {
+    TileShape t;
+    t.waves = waves;
+    t.doc_tile = 64 * waves * R;
+    t.q_tile = qpw * waves;
+    t.doc_groups = 1;
+    if ((t.q_tile <= want || qpw == 1) && shape_ok(t, kpl * 64)) return t.q_tile;
+  }
+  return waves;
+}
+
+// accumulators + entry state (static and one cursor copy) + member copy
+static int64_t gather_lds(const TileShape& t, int64_t ecap, int64_t pcap) {
+  return (int64_t)t.q_tile * t.doc_tile * 4 + ecap * (kEntryStaticBytes + kEntryDynBytes) +
+         pcap * 4 + 64;
 }
 
 TileShape choose_shape(const bm25_index* idx, int32_t n, int32_t max_qlen, int32_t k_max) {
   TileShape t;
   const int kpl = kpl_for(k_max);
   t.waves = 8;
-  t.q_tile = (kpl >= 8) ? 8 : 16;
   t.doc_tile = 1024;
+  t.q_tile = fit_q_tile(16, kpl, 8, 2);
+  // long queries: fewer queries per tile so that accumulators and entry state fit in LDS
+  auto fits = [&](const TileShape& s) {
+    const int64_t pc = std::min<int64_t>((int64_t)s.q_tile * max_qlen, kTileMaxPositions);
+    return gather_lds(s, pc + s.waves, pc) <= 96 * 1024;
+  };
+  while (!fits(t) && t.q_tile > t.waves) t.q_tile = fit_q_tile(t.q_tile / 2, kpl, 8, 2);
   const int64_t ntiles = std::max<int64_t>(1, (n + t.q_tile - 1) / t.q_tile);
   int64_t g = (1024 + ntiles - 1) / ntiles;
   g = ((g + 7) / 8) * 8;
   g = std::min<int64_t>(std::max<int64_t>(g, 8), 512);
-  g = std::min<int64_t>(g, std::max<int64_t>(1, idx->n_blocks));
+  const int64_t tiles = std::max<int64_t>(1, (idx->n_docs + t.doc_tile - 1) / t.doc_tile);
+  g = std::min<int64_t>(g, tiles);
   t.doc_groups = (int)g;
-  // keep the accumulator plus cursor slots within the LDS budget for long queries
-  const int64_t ecap = std::min<int64_t>((int64_t)t.q_tile * max_qlen, kTileMaxPositions) + 16;
-  while (gather_lds(t, ecap) > 96 * 1024 && t.doc_tile > 256) t.doc_tile /= 2;
   t.use_graph = 0;
+  t.sparse_only = 0;
   return t;
 }
 
@@ -245,17 +275,21 @@ int search_batch_impl(bm25_index* idx, const int32_t* q_ids, const int64_t* q_of
     auto it = idx->tuned.find(shape_class(n, info.max_qlen, k_max));
     t = (it != idx->tuned.end()) ? it->second : choose_shape(idx, n, info.max_qlen, k_max);
   }
+  if (!force && !shape_ok(t, k_max)) {
+    // a fixed or tuned plan made for smaller lists: keep its tile, shrink the query tile
+    t.q_tile = fit_q_tile(t.q_tile, kpl_for(k_max), t.waves,
+                          t.doc_tile / (64 * std::max(1, t.waves)));
+  }
   if (!shape_ok(t, k_max)) return set_error(BM25_E_INVAL, "invalid launch shape");
-  // register budget: at most 8 list registers (QPW * KPL) per lane
-  while ((t.q_tile / t.waves) * kpl_for(k_max) > 8 && t.q_tile > t.waves) t.q_tile /= 2;
-  const int W = t.waves, QPW = t.q_tile / t.waves, KPL = kpl_for(k_max), KP = 64 * KPL;
+  const int W = t.waves, QT = t.q_tile, R = t.doc_tile / (64 * t.waves);
+  const int KPL = kpl_for(k_max), KP = 64 * KPL;
 
   // query tiles: up to q_tile consecutive queries and kTileMaxPositions positions
   std::vector<int32_t> tile_q0;
   std::vector<int64_t> tile_e0;
   tile_q0.reserve(n / t.q_tile + 2);
   tile_e0.reserve(n / t.q_tile + 2);
-  int64_t ent = 0, ecap = 0;
+  int64_t ent = 0, ecap = 0, pcap = 0;
   int32_t q = 0;
   while (q < n) {
     tile_q0.push_back(q);
@@ -269,28 +303,31 @@ int search_batch_impl(bm25_index* idx, const int32_t* q_ids, const int64_t* q_of
     }
     ent += pos + W;
     ecap = std::max<int64_t>(ecap, pos + W);
+    pcap = std::max<int64_t>(pcap, pos);
   }
   const int32_t n_tiles = (int32_t)tile_q0.size();
   tile_q0.push_back(n);
   tile_e0.push_back(ent);
 
-  const int64_t lds = gather_lds(t, ecap);
+  const int64_t lds = gather_lds(t, ecap, pcap);
   if (lds > kMaxLdsBytes) return set_error(BM25_E_INVAL, "launch shape exceeds LDS");
   const int64_t G = t.doc_groups;
-  const int64_t nb = std::max<int64_t>(1, idx->n_blocks);
-  const int64_t group_docs = ((nb + G - 1) / G) * kSkipBlock;
+  const int64_t ntile_docs = std::max<int64_t>(1, (idx->n_docs + t.doc_tile - 1) / t.doc_tile);
+  const int64_t group_docs = ((ntile_docs + G - 1) / G) * t.doc_tile;
 
   BM25_RESERVE(sc.wave_e0, (size_t)n_tiles * (W + 1) * 4);
   BM25_RESERVE(sc.qstat, (size_t)n * 4);
   BM25_RESERVE(sc.entries, (size_t)std::max<int64_t>(ent, 1) * sizeof(Entry));
   BM25_RESERVE(sc.members, (size_t)std::max<int64_t>(info.positions, 1) * 4);
+  BM25_RESERVE(sc.dense_ent, (size_t)std::max<int64_t>(info.positions, 1) * sizeof(DenseEntry));
+  BM25_RESERVE(sc.dense_n, (size_t)n_tiles * 4);
   BM25_RESERVE(sc.cand, (size_t)n * G * KP * 8);
 
   Staged dev;
   rc = upload_plan(sc, s, n, n_tiles, q_off, k, k_max, tile_q0, tile_e0, dev);
   if (rc != BM25_OK) return rc;
 
-  IndexView ix = index_view(idx);
+  IndexView ix = index_view(idx, t.sparse_only != 0);
   BatchView bv;
   bv.q_ids = q_ids;
   bv.q_off = dev.q_off;
@@ -301,6 +338,8 @@ int search_batch_impl(bm25_index* idx, const int32_t* q_ids, const int64_t* q_of
   bv.wave_e0 = sc.wave_e0.as<int32_t>();
   bv.entries = sc.entries.as<Entry>();
   bv.members = sc.members.as<int32_t>();
+  bv.dense_ent = sc.dense_ent.as<DenseEntry>();
+  bv.dense_n = sc.dense_n.as<int32_t>();
   bv.n_queries = n;
   bv.n_tiles = n_tiles;
 
@@ -313,12 +352,12 @@ int search_batch_impl(bm25_index* idx, const int32_t* q_ids, const int64_t* q_of
   ga.cand = sc.cand.as<uint64_t>();
   ga.group_docs = group_docs;
   ga.n_groups = (int32_t)G;
-  ga.doc_tile = t.doc_tile;
   ga.ecap = (int32_t)ecap;
+  ga.pcap = (int32_t)pcap;
   hipEvent_t tb;
   rc = timed_begin(idx, s, &tb);
   if (rc != BM25_OK) return rc;
-  BM25_HIP(launch_gather(idx->params.store_dtype, W, QPW, KPL,
+  BM25_HIP(launch_gather(idx->params.store_dtype, W, QT, R, KPL,
                          dim3((unsigned)((int64_t)n_tiles * G)), (size_t)lds, s, ga));
   rc = timed_end(idx, s, tb);
   if (rc != BM25_OK) return rc;
@@ -349,11 +388,14 @@ int search_plain_impl(bm25_index* idx, const int32_t* q_ids, const int64_t* q_of
   if (rc != BM25_OK || n == 0) return rc;
   SearchScratch& sc = idx->plain_scratch;
   const int KPL = kpl_for(k_max), KP = 64 * KPL;
-  int W = 8;
-  int DT = std::max(1024, 2 * KP);
+  const int W = 8;
+  const int DT = 64 * 16;  // documents per wave tile (16 per lane)
   const int64_t ecap = (int64_t)info.max_qlen + 1;
-  while ((int64_t)W * DT * 4 + (int64_t)W * ecap * 4 > kMaxLdsBytes && W > 4) W /= 2;
-  const int64_t lds = (int64_t)W * DT * 4 + (int64_t)W * ecap * 4;
+  const int64_t pcap = std::max<int64_t>(info.max_qlen, 1);
+  // the list merge at the end reuses the accumulator region
+  const int64_t acc_bytes = std::max<int64_t>((int64_t)W * DT * 4, (int64_t)W * KP * 8);
+  const int64_t lds =
+      acc_bytes + ecap * (kEntryStaticBytes + (int64_t)W * kEntryDynBytes) + pcap * 4 + 64;
   if (lds > kMaxLdsBytes) return set_error(BM25_E_INVAL, "query too long for the per-query form");
   const int64_t nb = std::max<int64_t>(1, idx->n_blocks);
   const int64_t blocks_per_sweep = std::max<int64_t>(1, (nb + 2047) / 2048);
@@ -376,12 +418,14 @@ int search_plain_impl(bm25_index* idx, const int32_t* q_ids, const int64_t* q_of
   BM25_RESERVE(sc.qstat, (size_t)n * 4);
   BM25_RESERVE(sc.entries, (size_t)std::max<int64_t>(ent, 1) * sizeof(Entry));
   BM25_RESERVE(sc.members, (size_t)std::max<int64_t>(info.positions, 1) * 4);
+  BM25_RESERVE(sc.dense_ent, (size_t)std::max<int64_t>(info.positions, 1) * sizeof(DenseEntry));
+  BM25_RESERVE(sc.dense_n, (size_t)n * 4);
   BM25_RESERVE(sc.cand, (size_t)G * KP * 8);
   Staged dev;
   rc = upload_plan(sc, s, n, n, q_off, k, k_max, tile_q0, tile_e0, dev);
   if (rc != BM25_OK) return rc;
 
-  IndexView ix = index_view(idx);
+  IndexView ix = index_view(idx, idx->plan_fixed && idx->fixed_plan.sparse_only != 0);
   BatchView bv;
   bv.q_ids = q_ids;
   bv.q_off = dev.q_off;
@@ -392,6 +436,8 @@ int search_plain_impl(bm25_index* idx, const int32_t* q_ids, const int64_t* q_of
   bv.wave_e0 = sc.wave_e0.as<int32_t>();
   bv.entries = sc.entries.as<Entry>();
   bv.members = sc.members.as<int32_t>();
+  bv.dense_ent = sc.dense_ent.as<DenseEntry>();
+  bv.dense_n = sc.dense_n.as<int32_t>();
   bv.n_queries = n;
   bv.n_tiles = n;
   hipLaunchKernelGGL(k_plan, dim3(n), dim3(kPlanThreads), 0, s, ix, bv, 1);
@@ -403,8 +449,9 @@ int search_plain_impl(bm25_index* idx, const int32_t* q_ids, const int64_t* q_of
   sa.cand = sc.cand.as<uint64_t>();
   sa.sweep_docs = sweep_docs;
   sa.n_groups = (int32_t)G;
-  sa.doc_tile = DT;
+  sa.acc_bytes = (int32_t)acc_bytes;
   sa.ecap = (int32_t)ecap;
+  sa.pcap = (int32_t)pcap;
   MergeArgs ma;
   ma.cand = sc.cand.as<uint64_t>();
   ma.q_ids = q_ids;
@@ -474,7 +521,8 @@ extern "C" int bm25_search_set_plan(bm25_index* index, const bm25_tile_plan* pla
   t.doc_tile = plan->doc_tile;
   t.doc_groups = plan->doc_groups;
   t.use_graph = plan->use_graph;
-  if (!shape_ok(t, BM25_MAX_K)) return set_error(BM25_E_INVAL, "plan fields out of range");
+  t.sparse_only = plan->sparse_only;
+  if (!shape_ok(t, 64)) return set_error(BM25_E_INVAL, "plan fields out of range");
   index->fixed_plan = t;
   index->plan_fixed = true;
   return BM25_OK;
@@ -498,6 +546,7 @@ extern "C" int bm25_search_get_plan(const bm25_index* index, int32_t n_queries,
   plan->doc_tile = t.doc_tile;
   plan->doc_groups = t.doc_groups;
   plan->use_graph = t.use_graph;
+  plan->sparse_only = t.sparse_only;
   return BM25_OK;
 }
 
@@ -517,27 +566,28 @@ extern "C" int bm25_autotune(bm25_index* index, const int32_t* q_ids, const int6
   const TileShape base = choose_shape(index, n_queries, info.max_qlen, k_max);
   std::vector<TileShape> cands;
   const int kpl = kpl_for(k_max);
-  for (int waves : {4, 8})
-    for (int qpw : {1, 2, 4}) {
-      if (kpl >= 8 && qpw > 1) continue;
-      for (int dt : {512, 1024, 2048})
-        for (int gmul : {1, 2, 4}) {
-          TileShape t = base;
-          t.waves = waves;
-          t.q_tile = waves * qpw;
-          t.doc_tile = dt;
-          const int64_t ntiles = (n_queries + t.q_tile - 1) / t.q_tile;
-          int64_t gg = (1024 * gmul + ntiles - 1) / ntiles;
-          gg = ((gg + 7) / 8) * 8;
-          gg = std::min<int64_t>(std::max<int64_t>(gg, 8), 1024);
-          gg = std::min<int64_t>(gg, std::max<int64_t>(1, index->n_blocks));
-          t.doc_groups = (int)gg;
-          const int64_t ecap =
-              std::min<int64_t>((int64_t)t.q_tile * info.max_qlen, kTileMaxPositions) + 16;
-          if (gather_lds(t, ecap) > 128 * 1024) continue;
-          cands.push_back(t);
-        }
-    }
+  const int wr[3][2] = {{8, 2}, {4, 4}, {8, 4}};
+  for (const auto& shp : wr)
+    for (int qt : {shp[0], 2 * shp[0], 4 * shp[0]})
+      for (int gmul : {1, 2, 4}) {
+        TileShape t = base;
+        t.waves = shp[0];
+        t.doc_tile = 64 * shp[0] * shp[1];
+        t.q_tile = qt;
+        if (!shape_ok(t, k_max)) continue;
+        const int64_t ntiles = (n_queries + t.q_tile - 1) / t.q_tile;
+        int64_t gg = (1024 * gmul + ntiles - 1) / ntiles;
+        gg = ((gg + 7) / 8) * 8;
+        gg = std::min<int64_t>(std::max<int64_t>(gg, 8), 1024);
+        gg = std::min<int64_t>(gg, std::max<int64_t>(1, (index->n_docs + t.doc_tile - 1) /
+                                                             t.doc_tile));
+        t.doc_groups = (int)gg;
+        const int64_t pc =
+            std::min<int64_t>((int64_t)t.q_tile * info.max_qlen, kTileMaxPositions);
+        if (gather_lds(t, pc + t.waves, pc) > 128 * 1024) continue;
+        (void)kpl;
+        cands.push_back(t);
+      }
   hipEvent_t e0, e1;
   BM25_HIP(hipEventCreate(&e0));
   BM25_HIP(hipEventCreate(&e1));
@@ -570,6 +620,7 @@ extern "C" int bm25_autotune(bm25_index* index, const int32_t* q_ids, const int6
     best->doc_tile = best_t.doc_tile;
     best->doc_groups = best_t.doc_groups;
     best->use_graph = best_t.use_graph;
+    best->sparse_only = best_t.sparse_only;
   }
   clear_error();
   return BM25_OK;

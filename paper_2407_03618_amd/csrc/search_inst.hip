@@ -17,74 +17,77 @@ using namespace bm25dev;
 
 static constexpr int kMaxLds = 160 * 1024;
 
-template <int W, int QPW, int KPL>
+template <typename F>
+static hipError_t allow_lds(F fn, bool& done) {
+  if (done) return hipSuccess;
+  hipError_t e =
+      hipFuncSetAttribute((const void*)fn, hipFuncAttributeMaxDynamicSharedMemorySize, kMaxLds);
+  if (e == hipSuccess) done = true;
+  return e;
+}
+
+template <int W, int QT, int R, int KPL>
 static hipError_t gather_one(dim3 g, size_t sh, hipStream_t s, const GatherArgs& a) {
-  auto fn = k_gather<W, QPW, KPL, BM25_ST>;
+  auto fn = k_gather<W, QT, R, KPL, BM25_ST>;
   static bool attr = false;
-  if (!attr) {
-    hipError_t e = hipFuncSetAttribute((const void*)fn, hipFuncAttributeMaxDynamicSharedMemorySize,
-                                       kMaxLds);
-    if (e != hipSuccess) return e;
-    attr = true;
-  }
+  hipError_t e = allow_lds(fn, attr);
+  if (e != hipSuccess) return e;
   hipLaunchKernelGGL(fn, g, dim3(W * 64), sh, s, a);
   return hipGetLastError();
+}
+
+// Built shapes (W, R): (8, 2) and (4, 4) give 1024-document tiles, (8, 4) 2048. Queries per
+// tile QT = QPW * W with QPW in {1, 2, 4}; lists per wave QPW * KPL <= 8 registers when QPW > 1.
+template <int W, int R>
+static hipError_t gather_qt(int QT, int KPL, dim3 g, size_t sh, hipStream_t s,
+                            const GatherArgs& a) {
+#define BM25_Q(qpw, kpl) \
+  if (QT == (qpw) * W && KPL == kpl) return gather_one<W, (qpw) * W, R, kpl>(g, sh, s, a);
+  BM25_Q(1, 1)
+  BM25_Q(1, 2)
+  BM25_Q(1, 4)
+  BM25_Q(1, 8)
+  BM25_Q(1, 16)
+  BM25_Q(2, 1)
+  BM25_Q(2, 2)
+  BM25_Q(2, 4)
+  if constexpr (W * R <= 16) {
+    BM25_Q(4, 1)
+    BM25_Q(4, 2)
+  }
+#undef BM25_Q
+  return hipErrorInvalidValue;
+}
+
+hipError_t BM25_CAT(launch_gather_, BM25_ST_SUFFIX)(int W, int QT, int R, int KPL, dim3 g,
+                                                  size_t sh, hipStream_t s, const GatherArgs& a) {
+  if (W == 8 && R == 2) return gather_qt<8, 2>(QT, KPL, g, sh, s, a);
+  if (W == 4 && R == 4) return gather_qt<4, 4>(QT, KPL, g, sh, s, a);
+  if (W == 8 && R == 4) return gather_qt<8, 4>(QT, KPL, g, sh, s, a);
+  return hipErrorInvalidValue;
 }
 
 template <int W, int KPL>
 static hipError_t sweep_one(dim3 g, size_t sh, hipStream_t s, const SweepArgs& a) {
-  auto fn = k_sweep<W, KPL, BM25_ST>;
+  auto fn = k_sweep<W, 16, KPL, BM25_ST>;
   static bool attr = false;
-  if (!attr) {
-    hipError_t e = hipFuncSetAttribute((const void*)fn, hipFuncAttributeMaxDynamicSharedMemorySize,
-                                       kMaxLds);
-    if (e != hipSuccess) return e;
-    attr = true;
-  }
+  hipError_t e = allow_lds(fn, attr);
+  if (e != hipSuccess) return e;
   hipLaunchKernelGGL(fn, g, dim3(W * 64), sh, s, a);
   return hipGetLastError();
 }
 
-hipError_t BM25_CAT(launch_gather_, BM25_ST_SUFFIX)(int W, int QPW, int KPL, dim3 g, size_t sh,
-                                                  hipStream_t s, const GatherArgs& a) {
-#define BM25_G(w, q)                                          \
-  if (W == w && QPW == q) {                                   \
-    switch (KPL) {                                            \
-      case 1: return gather_one<w, q, 1>(g, sh, s, a);        \
-      case 2: return gather_one<w, q, 2>(g, sh, s, a);        \
-      case 4: return gather_one<w, q, 4>(g, sh, s, a);        \
-      case 8: return gather_one<w, q, 8>(g, sh, s, a);        \
-      case 16: return gather_one<w, q, 16>(g, sh, s, a);      \
-      default: return hipErrorInvalidValue;                   \
-    }                                                         \
-  }
-  BM25_G(4, 1)
-  BM25_G(4, 2)
-  BM25_G(4, 4)
-  BM25_G(8, 1)
-  BM25_G(8, 2)
-  BM25_G(8, 4)
-#undef BM25_G
-  return hipErrorInvalidValue;
-}
-
 hipError_t BM25_CAT(launch_sweep_, BM25_ST_SUFFIX)(int W, int KPL, dim3 g, size_t sh,
                                                  hipStream_t s, const SweepArgs& a) {
-#define BM25_S(w)                                          \
-  if (W == w) {                                            \
-    switch (KPL) {                                         \
-      case 1: return sweep_one<w, 1>(g, sh, s, a);         \
-      case 2: return sweep_one<w, 2>(g, sh, s, a);         \
-      case 4: return sweep_one<w, 4>(g, sh, s, a);         \
-      case 8: return sweep_one<w, 8>(g, sh, s, a);         \
-      case 16: return sweep_one<w, 16>(g, sh, s, a);       \
-      default: return hipErrorInvalidValue;                \
-    }                                                      \
+  if (W != 8) return hipErrorInvalidValue;
+  switch (KPL) {
+    case 1: return sweep_one<8, 1>(g, sh, s, a);
+    case 2: return sweep_one<8, 2>(g, sh, s, a);
+    case 4: return sweep_one<8, 4>(g, sh, s, a);
+    case 8: return sweep_one<8, 8>(g, sh, s, a);
+    case 16: return sweep_one<8, 16>(g, sh, s, a);
+    default: return hipErrorInvalidValue;
   }
-  BM25_S(4)
-  BM25_S(8)
-#undef BM25_S
-  return hipErrorInvalidValue;
 }
 
 }  // namespace bm25

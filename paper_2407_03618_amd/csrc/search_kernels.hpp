@@ -46,10 +46,22 @@ struct IndexView {
   const void* data;
   const int32_t* long_id;
   const uint32_t* skip;
-  const float* theta32;  // nullptr for sparse variants
+  const float* theta32;   // nullptr for sparse variants
+  const int32_t* dense_id;  // dense row of each token or -1; nullptr: no dense rows used
+  const void* dense;      // [n_dense][n_pad] stored scores
   int64_t n_docs;
   int64_t n_blocks;
+  int64_t n_pad;
   int32_t vocab;
+};
+
+// A dense-row token of a query tile: its stored scores are added, times `mult`, to every query
+// of the tile whose bit is set in `qmask` (one entry per distinct multiplicity).
+struct DenseEntry {
+  int32_t row;
+  uint32_t qmask;
+  float mult;
+  int32_t token;
 };
 
 struct BatchView {
@@ -62,6 +74,8 @@ struct BatchView {
   int32_t* wave_e0;        // [n_tiles * (W+1)]: entry range of each wave inside the tile
   Entry* entries;
   int32_t* members;        // q_local | mult << 16
+  DenseEntry* dense_ent;   // per tile, at the tile's first position
+  int32_t* dense_n;        // [n_tiles]: dense entries of each tile
   int32_t n_queries;
   int32_t n_tiles;
 };
@@ -146,6 +160,7 @@ struct PlanSmem {
   int32_t tok[kPlanSort];
   uint32_t parts[kPlanSort + 1];         // per distinct token: number of entries
   uint32_t tmp[kPlanSort + 1];
+  uint32_t dcnt[kPlanSort + 1];          // per distinct token: dense entries
   int64_t qoff[65];
   uint32_t err[64];
   float cost_sum[4];
@@ -256,9 +271,55 @@ __global__ __launch_bounds__(kPlanThreads) void k_plan(IndexView ix, BatchView b
     bv.members[p0 + m] = (int32_t)(ql | (mult << 16));
   }
 
-  // 4. cost of each token and number of entries it is split into
+  // 3b. dense tokens: one entry per distinct multiplicity, with the mask of its queries
+  auto is_dense = [&](uint32_t u) {
+    return ix.dense_id != nullptr && ix.dense_id[sm.tok[u]] >= 0;
+  };
+  for (int u = tid; u < kPlanSort; u += kPlanThreads) {
+    uint32_t cnt = 0;
+    if ((uint32_t)u < n_tok && is_dense((uint32_t)u)) {
+      const uint32_t m0 = sm.first_member[u], m1 = sm.first_member[u + 1];
+      for (uint32_t m = m0; m < m1; ++m) {
+        const uint32_t mult = sm.pos_of_member[m + 1] - sm.pos_of_member[m];
+        bool seen = false;
+        for (uint32_t mm = m0; mm < m; ++mm)
+          seen |= (sm.pos_of_member[mm + 1] - sm.pos_of_member[mm]) == mult;
+        cnt += seen ? 0u : 1u;
+      }
+    }
+    sm.dcnt[u] = cnt;
+  }
+  __syncthreads();
+  const uint32_t n_dent = lds_scan_u32(sm.dcnt, kPlanSort, sm.lds4);
+  for (uint32_t u = tid; u < n_tok; u += kPlanThreads) {
+    if (!is_dense(u)) continue;
+    const uint32_t m0 = sm.first_member[u], m1 = sm.first_member[u + 1];
+    uint32_t o = sm.dcnt[u];
+    for (uint32_t m = m0; m < m1; ++m) {
+      const uint32_t mult = sm.pos_of_member[m + 1] - sm.pos_of_member[m];
+      bool seen = false;
+      for (uint32_t mm = m0; mm < m; ++mm)
+        seen |= (sm.pos_of_member[mm + 1] - sm.pos_of_member[mm]) == mult;
+      if (seen) continue;
+      uint32_t mask = 0;
+      for (uint32_t mm = m; mm < m1; ++mm)
+        if (sm.pos_of_member[mm + 1] - sm.pos_of_member[mm] == mult)
+          mask |= 1u << (uint32_t)(sm.key[sm.pos_of_member[mm]] & 31u);
+      DenseEntry de;
+      de.row = ix.dense_id[sm.tok[u]];
+      de.qmask = mask;
+      de.mult = (float)mult;
+      de.token = sm.tok[u];
+      bv.dense_ent[p0 + o] = de;
+      ++o;
+    }
+  }
+  if (tid == 0) bv.dense_n[tile] = (int32_t)n_dent;
+
+  // 4. cost of each sparse token and number of entries it is split into
   float local = 0.f;
   for (uint32_t u = tid; u < n_tok; u += kPlanThreads) {
+    if (is_dense(u)) continue;
     const int32_t t = sm.tok[u];
     const float df = (float)(ix.indptr[t + 1] - ix.indptr[t]);
     const float mc = (float)(sm.first_member[u + 1] - sm.first_member[u]);
@@ -273,7 +334,7 @@ __global__ __launch_bounds__(kPlanThreads) void k_plan(IndexView ix, BatchView b
   const float target = total / (float)W;
   for (int u = tid; u < kPlanSort; u += kPlanThreads) {
     uint32_t parts = 0;
-    if ((uint32_t)u < n_tok) {
+    if ((uint32_t)u < n_tok && !is_dense((uint32_t)u)) {
       const int32_t t = sm.tok[u];
       const int64_t df = ix.indptr[t + 1] - ix.indptr[t];
       const uint32_t mc = sm.first_member[u + 1] - sm.first_member[u];
@@ -374,42 +435,402 @@ __global__ __launch_bounds__(kPlanThreads) void k_plan(IndexView ix, BatchView b
 // Long rows read the skip table (d0 is a multiple of the skip block). Other rows (fewer than
 // 4096 entries) compare d0 against every 64th entry of the row, then scan one 64-entry chunk.
 // Whole wave, uniform arguments.
-__device__ __forceinline__ int64_t find_cursor(const IndexView& ix, const Entry& e, int64_t d0) {
-  if (d0 <= 0) return 0;
-  const int64_t len = e.row_hi - e.row_lo;
-  if (len == 0) return 0;
-  if (e.long_id >= 0) {
-    const int64_t b = d0 / kSkipBlockDev;
-    return (int64_t)ix.skip[(int64_t)e.long_id * (ix.n_blocks + 1) + b];
-  }
+__device__ __forceinline__ int32_t find_cursor(const IndexView& ix, int64_t row_lo, int32_t len,
+                                               int32_t long_id, int64_t d0) {
+  if (d0 <= 0 || len == 0) return 0;
+  if (long_id >= 0)
+    return (int32_t)ix.skip[(int64_t)long_id * (ix.n_blocks + 1) + d0 / kSkipBlockDev];
   const int l = lane();
+  const int64_t row_hi = row_lo + len;
   // samples at absolute positions 64*j inside [row_lo, row_hi)
-  const int64_t j0 = (e.row_lo + 63) >> 6;
-  const int64_t j1 = (e.row_hi - 1) >> 6;  // inclusive
+  const int64_t j0 = (row_lo + 63) >> 6;
+  const int64_t j1 = (row_hi - 1) >> 6;  // inclusive
   const int64_t js = j0 + l;
   const bool has = js <= j1;
   const int32_t sv = has ? ix.indices[js << 6] : INT32_MAX;
   const int c_s = __popcll(ballot(has && sv < d0));
   // chunk to scan: before the first sample if c_s == 0, else from the last sample below d0
-  const int64_t from = (c_s == 0) ? e.row_lo : ((j0 + c_s - 1) << 6);
+  const int64_t from = (c_s == 0) ? row_lo : ((j0 + c_s - 1) << 6);
   const int64_t p = from + l;
-  const bool in = p < e.row_hi && p < from + 64;
+  const bool in = p < row_hi && p < from + 64;
   const int32_t v = in ? ix.indices[p] : INT32_MAX;
   const int c = __popcll(ballot(in && v < d0));
-  return from + c - e.row_lo;
+  return (int32_t)(from + c - row_lo);
 }
 
 // ------------------------------------------------------------------------------------------
-// Batched gather + top-k. Workgroup = (query tile, doc group); W waves; QPW queries per wave.
+// Sweep state of the entries (query tokens) a wave walks through, structure of arrays in LDS:
+// static fields (row start, row length, skip-table row, member range) and the dynamic cursor
+// (offset of the next unconsumed entry of the row) plus, for rows without a skip table, the
+// document id at the cursor (INT32_MAX past the end), so that a tile without postings of that
+// row costs no memory access.
+struct EntryState {
+  int64_t* row_lo;
+  int32_t* len;
+  int32_t* lid;
+  int32_t* mem;  // member offset (relative to the LDS member copy) | member count << 16
+  int32_t* cur;
+  int32_t* nd;
+};
+
+constexpr int kEntryStaticBytes = 8 + 4 + 4 + 4;
+constexpr int kEntryDynBytes = 4 + 4;
+
+__device__ __forceinline__ EntryState carve_state(uint8_t* base, int cap, int dyn_copies,
+                                                  int dyn_index) {
+  EntryState st;
+  st.row_lo = reinterpret_cast<int64_t*>(base);
+  st.len = reinterpret_cast<int32_t*>(base + (size_t)cap * 8);
+  st.lid = st.len + cap;
+  st.mem = st.lid + cap;
+  int32_t* dyn = st.mem + cap;
+  st.cur = dyn + (size_t)dyn_index * 2 * cap;
+  st.nd = st.cur + cap;
+  (void)dyn_copies;
+  return st;
+}
+
+// Loads static fields of entries [e_lo, e_hi) (lane-parallel) from the planner table.
+__device__ __forceinline__ void load_static(const Entry* ents, int e_lo, int e_hi,
+                                            int64_t mem_base, const EntryState& st) {
+  for (int j = e_lo + lane(); j < e_hi; j += 64) {
+    const Entry en = ents[j];
+    st.row_lo[j] = en.row_lo;
+    st.len[j] = (int32_t)(en.row_hi - en.row_lo);
+    st.lid[j] = en.long_id;
+    st.mem[j] = (int32_t)((en.mem_off - mem_base) | ((int64_t)en.mem_cnt << 16));
+  }
+}
+
+// Cursor and next document at the sweep start d0 for entries [e_lo, e_hi) (whole wave).
+__device__ __forceinline__ void init_cursors(const IndexView& ix, int e_lo, int e_hi, int64_t d0,
+                                             const EntryState& st) {
+  for (int j = e_lo; j < e_hi; ++j) {
+    const int64_t row_lo = st.row_lo[j];
+    const int32_t len = st.len[j];
+    const int32_t c = find_cursor(ix, row_lo, len, st.lid[j], d0);
+    if (lane() == 0) {
+      st.cur[j] = c;
+      st.nd[j] = (c < len) ? ix.indices[row_lo + c] : INT32_MAX;
+    }
+  }
+}
+
+// Adds the postings of entries [e_lo, e_hi) that fall in the document tile [t0, t1) into the
+// accumulator rows acc[q * DT + (d - t0)] of their member queries.
+//
+// Long rows take the tile's segment end from the skip table (tiles start and end on skip-block
+// boundaries, or at N). Their segments are cut into 64-posting chunks and the chunks of all the
+// wave's long rows are walked as one flat list, kChunksInFlight at a time: the loads of those
+// chunks are issued together (addresses are clamped inside the row instead of predicated, so no
+// load waits behind a branch), then each chunk's postings are added for every member query of
+// its entry. Rows without a skip table stream from their cursor until the first document >= t1.
+constexpr int kChunksInFlight = 4;
+
+template <typename ST>
+__device__ __forceinline__ void accumulate_tile(const IndexView& ix, const EntryState& st,
+                                                int e_lo, int e_hi, const int32_t* mem_lds,
+                                                float* acc, int DT, int64_t t0, int64_t t1) {
+  constexpr int U = kChunksInFlight;
+  const int l = lane();
+  const typename ST::T* data = reinterpret_cast<const typename ST::T*>(ix.data);
+  const int32_t t0i = (int32_t)t0, t1i = (int32_t)t1;
+  const bool at_end = t1 >= ix.n_docs;
+  const int64_t b1 = t1 / kSkipBlockDev;
+  for (int g0 = e_lo; g0 < e_hi; g0 += 64) {
+    const int j = g0 + l;
+    const bool ve = j < e_hi;
+    int32_t cur = ve ? st.cur[j] : 0;
+    const int32_t len = ve ? st.len[j] : 0;
+    const int32_t lid = ve ? st.lid[j] : -1;
+    int32_t nd = ve ? st.nd[j] : INT32_MAX;
+    const int64_t rlo = ve ? st.row_lo[j] : 0;
+    const int32_t mw = ve ? st.mem[j] : 0;
+    int32_t end = cur;
+    if (ve && lid >= 0)
+      end = at_end ? len : (int32_t)ix.skip[(int64_t)lid * (ix.n_blocks + 1) + b1];
+    // chunks of the long rows, flattened across the wave's entries
+    const int32_t nch = (lid >= 0 && end > cur) ? ((end - cur + 63) >> 6) : 0;
+    int32_t incl = nch;
+#pragma unroll
+    for (int o = 1; o < 64; o <<= 1) {
+      const int32_t y = (int32_t)bperm((uint32_t)incl, (l - o) & 63);
+      if (l >= o) incl += y;
+    }
+    const int32_t base = incl - nch;
+    const int32_t C = (int32_t)readlane((uint32_t)incl, 63);
+    for (int32_t c0 = 0; c0 < C; c0 += U) {
+      int32_t rel[U];
+      float sv[U];
+      int32_t memw[U];
+#pragma unroll
+      for (int u = 0; u < U; ++u) {
+        const int32_t c = c0 + u;
+        const bool act = c < C;
+        const uint64_t own = ballot(nch > 0 && base <= c);
+        const int src = act ? 63 - __builtin_clzll(own) : 0;
+        const int32_t kk = c - (int32_t)readlane((uint32_t)base, src);
+        const int64_t row = (int64_t)readlane64((uint64_t)rlo, src);
+        const int32_t cs = (int32_t)readlane((uint32_t)cur, src);
+        const int32_t ce = (int32_t)readlane((uint32_t)end, src);
+        memw[u] = act ? (int32_t)readlane((uint32_t)mw, src) : 0;
+        const int32_t p = cs + 64 * kk + l;
+        const bool valid = act && p < ce;
+        const int64_t off = row + (valid ? p : cs);
+        const int32_t d = ix.indices[off];
+        sv[u] = ST::load(data, off);
+        const int32_t r = d - t0i;
+        rel[u] = (valid && r >= 0 && r < DT) ? r : -1;
+      }
+#pragma unroll
+      for (int u = 0; u < U; ++u) {
+        const uint32_t w = (uint32_t)memw[u];
+        const int mcnt = (int)(w >> 16);
+        const int32_t mem = (l < mcnt) ? mem_lds[(w & 0xFFFFu) + l] : 0;
+        for (int m = 0; m < mcnt; ++m) {
+          const uint32_t mm = readlane((uint32_t)mem, m);
+          const float v = sv[u] * (float)(mm >> 16);
+          if (rel[u] >= 0) atomicAdd(acc + (int)(mm & 0xFFFFu) * DT + rel[u], v);
+        }
+      }
+    }
+    if (lid >= 0) cur = end;
+    // rows without a skip table that have a posting in this tile
+    uint64_t pending = ballot(ve && lid < 0 && nd < t1i);
+    while (pending) {
+      const int src = __builtin_ctzll(pending);
+      pending &= pending - 1;
+      const int64_t row = (int64_t)readlane64((uint64_t)rlo, src);
+      const uint32_t w = readlane((uint32_t)mw, src);
+      const int mcnt = (int)(w >> 16);
+      const int32_t mem = (l < mcnt) ? mem_lds[(w & 0xFFFFu) + l] : 0;
+      const int32_t L = (int32_t)readlane((uint32_t)len, src);
+      int32_t c = (int32_t)readlane((uint32_t)cur, src);
+      int32_t ndnew;
+      while (true) {
+        const int32_t o = c + l;
+        const bool in_row = o < L;
+        const int64_t off = row + (in_row ? o : 0);
+        const int32_t dl = ix.indices[off];
+        const float s = ST::load(data, off);
+        const int32_t d = in_row ? dl : INT32_MAX;
+        const bool v = d < t1i;
+        const int32_t r = d - t0i;
+        const bool ok = v && r >= 0;
+        for (int m = 0; m < mcnt; ++m) {
+          const uint32_t mm = readlane((uint32_t)mem, m);
+          if (ok) atomicAdd(acc + (int)(mm & 0xFFFFu) * DT + r, s * (float)(mm >> 16));
+        }
+        const int n = __popcll(ballot(v));
+        c += n;
+        if (n < 64) {
+          ndnew = (int32_t)readlane((uint32_t)d, n);
+          break;
+        }
+      }
+      if (l == src) {
+        cur = c;
+        nd = ndnew;
+      }
+    }
+    if (ve) {
+      st.cur[j] = cur;
+      st.nd[j] = nd;
+    }
+  }
+}
+
+// Loads R consecutive stored scores (R * sizeof(T) bytes, aligned) and widens them to FP32.
+template <typename ST, int R>
+__device__ __forceinline__ void load_dense(const typename ST::T* p, float* v) {
+  constexpr int NW = R * (int)sizeof(typename ST::T) / 4;
+  static_assert(NW >= 1 && (NW == 1 || NW % 2 == 0), "unsupported dense width");
+  uint32_t w[NW];
+  const uint32_t* q = reinterpret_cast<const uint32_t*>(p);
+  if constexpr (NW % 4 == 0) {
+#pragma unroll
+    for (int i = 0; i < NW / 4; ++i) {
+      const uint4 x = reinterpret_cast<const uint4*>(q)[i];
+      w[4 * i] = x.x;
+      w[4 * i + 1] = x.y;
+      w[4 * i + 2] = x.z;
+      w[4 * i + 3] = x.w;
+    }
+  } else if constexpr (NW == 2) {
+    const uint2 x = reinterpret_cast<const uint2*>(q)[0];
+    w[0] = x.x;
+    w[1] = x.y;
+  } else {
+    w[0] = q[0];
+  }
+  if constexpr (sizeof(typename ST::T) == 4) {
+#pragma unroll
+    for (int i = 0; i < R; ++i) v[i] = __uint_as_float(w[i]);
+  } else {
+#pragma unroll
+    for (int i = 0; i < R / 2; ++i) {
+      v[2 * i] = ST::widen_lo(w[i]);
+      v[2 * i + 1] = ST::widen_hi(w[i]);
+    }
+  }
+}
+
+// Reads R consecutive floats of an LDS row and clears them.
+template <int R>
+__device__ __forceinline__ void take_lds(float* p, float* v) {
+  if constexpr (R % 4 == 0) {
+#pragma unroll
+    for (int i = 0; i < R / 4; ++i) {
+      const float4 x = reinterpret_cast<float4*>(p)[i];
+      reinterpret_cast<float4*>(p)[i] = make_float4(0.f, 0.f, 0.f, 0.f);
+      v[4 * i] = x.x;
+      v[4 * i + 1] = x.y;
+      v[4 * i + 2] = x.z;
+      v[4 * i + 3] = x.w;
+    }
+  } else {
+    static_assert(R == 2, "unsupported width");
+    const float2 x = reinterpret_cast<float2*>(p)[0];
+    reinterpret_cast<float2*>(p)[0] = make_float2(0.f, 0.f);
+    v[0] = x.x;
+    v[1] = x.y;
+  }
+}
+
+// Adds the dense-row entries [0, n) to the register accumulators acc[q][r] of the lane's R
+// documents starting at tile document `first`. Loads run U = max(2, 16 / R) entries at a time
+// (16 values per lane) and the next group's loads are issued before the current group's
+// additions.
+template <typename ST, int QT, int R>
+__device__ __forceinline__ void accumulate_dense(const IndexView& ix, const DenseEntry* de, int n,
+                                                 int64_t first, float (&acc)[QT][R]) {
+  constexpr int U = (16 / R) > 2 ? (16 / R) : 2;
+  const typename ST::T* dense = reinterpret_cast<const typename ST::T*>(ix.dense) + first;
+  float v[2][U][R];
+  auto load_group = [&](int e0, float (&dst)[U][R]) {
+#pragma unroll
+    for (int u = 0; u < U; ++u) {
+      const int e = (e0 + u < n) ? e0 + u : n - 1;  // clamped: always a valid row
+      load_dense<ST, R>(dense + (int64_t)de[e].row * ix.n_pad, dst[u]);
+    }
+  };
+  if (n <= 0) return;
+  load_group(0, v[0]);
+  for (int e0 = 0; e0 < n; e0 += 2 * U) {
+#pragma unroll
+    for (int h = 0; h < 2; ++h) {
+      const int eg = e0 + h * U;
+      if (eg >= n) break;
+      if (eg + U < n) load_group(eg + U, v[h ^ 1]);
+#pragma unroll
+      for (int u = 0; u < U; ++u) {
+        if (eg + u < n) {
+          const uint32_t mask = de[eg + u].qmask;
+          const float mult = de[eg + u].mult;
+#pragma unroll
+          for (int q = 0; q < QT; ++q) {
+            if ((mask >> q) & 1u) {
+#pragma unroll
+              for (int r = 0; r < R; ++r) acc[q][r] = fmaf(mult, v[h][u][r], acc[q][r]);
+            }
+          }
+        }
+      }
+    }
+  }
+}
+
+// Filters one accumulator row of a tile against the wave's current k-th key, offers the
+// survivors to the list and clears the row. A plain FP32 comparison with the k-th score
+// rejects most values; only chunks with a candidate build 64-bit keys.
+template <int KPL>
+__device__ __forceinline__ void select_row(float* rowp, int DT, int64_t t0, int64_t t1,
+                                           TopList<KPL>& L, int cap, uint64_t& thr) {
+  const int l = lane();
+  float4* row = reinterpret_cast<float4*>(rowp);
+  float thr_s = (thr == 0) ? -INFINITY : key_score(thr);
+  for (int i = l; i < DT / 4; i += 64) {
+    const float4 v4 = row[i];
+    row[i] = make_float4(0.f, 0.f, 0.f, 0.f);
+    const bool p = (v4.x >= thr_s) || (v4.y >= thr_s) || (v4.z >= thr_s) || (v4.w >= thr_s);
+    if (ballot(p)) {
+      const int64_t db = t0 + 4 * i;
+      const float vs[4] = {v4.x, v4.y, v4.z, v4.w};
+#pragma unroll
+      for (int c = 0; c < 4; ++c) {
+        const int64_t doc = db + c;
+        const uint64_t key = (doc < t1) ? make_key(vs[c], (uint32_t)doc) : 0ull;
+        L.offer(key, cap, thr);
+      }
+      thr_s = (thr == 0) ? -INFINITY : key_score(thr);
+    }
+  }
+}
+
+// Adds R register values into an LDS row (the lane owns these documents) and clears them.
+template <int R>
+__device__ __forceinline__ void fold_lds(float* p, float* v) {
+  if constexpr (R % 4 == 0) {
+#pragma unroll
+    for (int i = 0; i < R / 4; ++i) {
+      float4 x = reinterpret_cast<float4*>(p)[i];
+      x.x += v[4 * i];
+      x.y += v[4 * i + 1];
+      x.z += v[4 * i + 2];
+      x.w += v[4 * i + 3];
+      reinterpret_cast<float4*>(p)[i] = x;
+    }
+  } else {
+    static_assert(R == 2, "unsupported width");
+    float2 x = reinterpret_cast<float2*>(p)[0];
+    x.x += v[0];
+    x.y += v[1];
+    reinterpret_cast<float2*>(p)[0] = x;
+  }
+#pragma unroll
+  for (int r = 0; r < R; ++r) v[r] = 0.f;
+}
+
+// Offers the lane's R documents of one query (scores v, documents first..first+R-1, only those
+// below t1) to the wave's list when any of them reaches the list's k-th score.
+template <int KPL, int R>
+__device__ __forceinline__ void select_regs(const float* v, int64_t first, int64_t t1,
+                                            TopList<KPL>& L, int cap, uint64_t& thr,
+                                            float& thr_s) {
+  bool p = false;
+#pragma unroll
+  for (int r = 0; r < R; ++r) p |= v[r] >= thr_s;
+  if (ballot(p)) {
+#pragma unroll
+    for (int r = 0; r < R; ++r) {
+      const int64_t doc = first + r;
+      const uint64_t key = (doc < t1) ? make_key(v[r], (uint32_t)doc) : 0ull;
+      L.offer(key, cap, thr);
+    }
+    thr_s = (thr == 0) ? -INFINITY : key_score(thr);
+  }
+}
+
+// ------------------------------------------------------------------------------------------
+// Batched gather + top-k. Workgroup = (query tile of up to QT queries, doc group), W waves.
+// A tile spans DT = W * 64 * R documents; lane l of wave w owns documents w*64*R + l*R .. +R-1
+// of the tile for every query of the tile, with FP32 accumulators in registers. Dense-row
+// tokens are added straight into the registers; the other tokens' postings are added into an
+// LDS accumulator row per query. Once per tile the lanes fold their registers into those rows
+// (each lane owns its documents: no atomics), and the wave owning a query filters its row
+// against the query's k-th key (QPW = QT / W queries per wave, one list each).
+//
+// LDS: accumulator rows [QT][DT] | entry static fields [ecap] | cursors [ecap] |
+//      member copy [pcap].
 
 struct GatherArgs {
   IndexView ix;
   BatchView bv;
   uint64_t* cand;       // [n_queries][n_groups][KP]
-  int64_t group_docs;   // multiple of the skip block
+  int64_t group_docs;   // multiple of the skip block and of DT
   int32_t n_groups;
-  int32_t doc_tile;     // multiple of 256
-  int32_t ecap;         // cursor slots per workgroup (>= entries of any tile)
+  int32_t ecap;         // entry slots per workgroup (>= sparse entries of any tile)
+  int32_t pcap;         // member slots per workgroup (>= positions of any tile)
 };
 
 __device__ __forceinline__ void map_block(int bid, int n_groups, int& tile, int& group) {
@@ -427,14 +848,18 @@ __device__ __forceinline__ void map_block(int bid, int n_groups, int& tile, int&
   }
 }
 
-template <int W, int QPW, int KPL, typename ST>
+template <int W, int QT, int R, int KPL, typename ST>
 __global__ __launch_bounds__(W * 64) void k_gather(GatherArgs a) {
-  constexpr int QT = W * QPW;
+  constexpr int DT = W * 64 * R;
   constexpr int KP = KPL * 64;
+  constexpr int QPW = QT / W;
+  static_assert(QT % W == 0, "queries must divide evenly over the waves");
   extern __shared__ __align__(16) uint8_t smem[];
-  const int DT = a.doc_tile;
-  float* acc = reinterpret_cast<float*>(smem);
-  int32_t* cursor = reinterpret_cast<int32_t*>(smem + (size_t)QT * DT * 4);
+  float* rows = reinterpret_cast<float*>(smem);
+  uint8_t* sbase = smem + (size_t)QT * DT * 4;
+  const EntryState st = carve_state(sbase, a.ecap, 1, 0);
+  int32_t* mem_lds = reinterpret_cast<int32_t*>(sbase + (size_t)a.ecap *
+                                                           (kEntryStaticBytes + kEntryDynBytes));
 
   int tile, group;
   map_block(blockIdx.x, a.n_groups, tile, group);
@@ -444,23 +869,28 @@ __global__ __launch_bounds__(W * 64) void k_gather(GatherArgs a) {
   const IndexView& ix = a.ix;
   const int q0 = bv.tile_q0[tile];
   const int nq = bv.tile_q0[tile + 1] - q0;
+  const int64_t p0 = bv.q_off[q0];
+  const int P = (int)(bv.q_off[q0 + nq] - p0);
   const int64_t e_base = bv.tile_e0[tile];
   const int32_t* we = bv.wave_e0 + (int64_t)tile * (W + 1);
   const int e_lo = we[w], e_hi = we[w + 1];
+  const DenseEntry* dent = bv.dense_ent + p0;
+  const int n_dense = bv.dense_n[tile];
   const int64_t d_lo = (int64_t)group * a.group_docs;
   const int64_t d_hi = (d_lo + a.group_docs < ix.n_docs) ? d_lo + a.group_docs : ix.n_docs;
-  const typename ST::T* data = reinterpret_cast<const typename ST::T*>(ix.data);
 
-  for (int e = e_lo; e < e_hi; ++e) {
-    const Entry en = bv.entries[e_base + e];
-    const int64_t c = (d_lo < d_hi) ? find_cursor(ix, en, d_lo) : 0;
-    if (l == 0) cursor[e] = (int32_t)c;
-  }
+  for (int i = threadIdx.x; i < P; i += W * 64) mem_lds[i] = bv.members[p0 + i];
+  load_static(bv.entries + e_base, e_lo, e_hi, p0, st);
+  if (d_lo < d_hi) init_cursors(ix, e_lo, e_hi, d_lo, st);
   {
-    float4* a4 = reinterpret_cast<float4*>(acc);
-    const int n4 = QT * DT / 4;
-    for (int i = threadIdx.x; i < n4; i += W * 64) a4[i] = make_float4(0.f, 0.f, 0.f, 0.f);
+    float4* a4 = reinterpret_cast<float4*>(rows);
+    for (int i = threadIdx.x; i < QT * DT / 4; i += W * 64) a4[i] = make_float4(0.f, 0.f, 0.f, 0.f);
   }
+  float acc[QT][R];
+#pragma unroll
+  for (int q = 0; q < QT; ++q)
+#pragma unroll
+    for (int r = 0; r < R; ++r) acc[q][r] = 0.f;
   TopList<KPL> L[QPW];
   uint64_t thr[QPW];
   int cap[QPW];
@@ -472,55 +902,23 @@ __global__ __launch_bounds__(W * 64) void k_gather(GatherArgs a) {
     cap[j] = (ql < nq) ? bv.q_k[q0 + ql] : 1;
   }
   __syncthreads();
+  const int first = w * 64 * R + l * R;
 
   for (int64_t t0 = d_lo; t0 < d_hi; t0 += DT) {
     const int64_t t1 = (t0 + DT < d_hi) ? t0 + DT : d_hi;
-    const int32_t t1i = (int32_t)t1;
-    // accumulate this wave's entries into the tile
-    for (int e = e_lo; e < e_hi; ++e) {
-      const Entry en = bv.entries[e_base + e];
-      const int64_t len = en.row_hi - en.row_lo;
-      int64_t c = cursor[e];
-      const int32_t mem = (l < en.mem_cnt) ? bv.members[en.mem_off + l] : 0;
-      while (true) {
-        const int64_t off = c + l;
-        const bool in_row = off < len;
-        const int32_t d = in_row ? ix.indices[en.row_lo + off] : INT32_MAX;
-        const bool v = d < t1i && d >= (int32_t)t0;
-        const float s = v ? ST::load(data, en.row_lo + off) : 0.f;
-        const int rel = d - (int32_t)t0;
-        for (int m = 0; m < en.mem_cnt; ++m) {
-          const uint32_t mm = readlane((uint32_t)mem, m);
-          const int ql = (int)(mm & 0xFFFFu);
-          const float mult = (float)(mm >> 16);
-          if (v) atomicAdd(&acc[ql * DT + rel], s * mult);
-        }
-        const int n = __popcll(ballot(v));
-        c += n;
-        if (n < 64) break;
-      }
-      if (l == 0) cursor[e] = (int32_t)c;
-    }
+    accumulate_tile<ST>(ix, st, e_lo, e_hi, mem_lds, rows, DT, t0, t1);
+    accumulate_dense<ST, QT, R>(ix, dent, n_dense, t0 + first, acc);
     __syncthreads();
-    // select: filter each owned query's row against its k-th key, then clear it
+    if (n_dense > 0) {
+#pragma unroll
+      for (int q = 0; q < QT; ++q)
+        if (q < nq) fold_lds<R>(rows + q * DT + first, acc[q]);
+      __syncthreads();
+    }
 #pragma unroll
     for (int j = 0; j < QPW; ++j) {
       const int ql = w * QPW + j;
-      if (ql < nq) {
-        float4* row = reinterpret_cast<float4*>(acc + ql * DT);
-        for (int i = l; i < DT / 4; i += 64) {
-          const float4 v4 = row[i];
-          row[i] = make_float4(0.f, 0.f, 0.f, 0.f);
-          const int64_t db = t0 + 4 * i;
-          const float vs[4] = {v4.x, v4.y, v4.z, v4.w};
-#pragma unroll
-          for (int c = 0; c < 4; ++c) {
-            const int64_t doc = db + c;
-            const uint64_t key = (doc < t1) ? make_key(vs[c], (uint32_t)doc) : 0ull;
-            L[j].offer(key, cap[j], thr[j]);
-          }
-        }
-      }
+      if (ql < nq) select_row<KPL>(rows + ql * DT, DT, t0, t1, L[j], cap[j], thr[j]);
     }
     __syncthreads();
   }
@@ -536,8 +934,12 @@ __global__ __launch_bounds__(W * 64) void k_gather(GatherArgs a) {
 }
 
 // ------------------------------------------------------------------------------------------
-// Per-query sweep: one query; every wave of every workgroup sweeps its own document range with
-// a private accumulator tile; the waves of a workgroup merge their lists at the end.
+// Per-query sweep: one query; every wave of every workgroup sweeps its own document range in
+// tiles of 64 * RS documents (RS per lane, in registers) with a private LDS accumulator for the
+// sparse rows; the waves of a workgroup merge their lists at the end.
+//
+// LDS: max(sparse accumulators [W][64*RS], lists [W][KP]) | entry static fields [ecap] |
+//      cursors [W][ecap] | members [pcap].
 
 struct SweepArgs {
   IndexView ix;
@@ -546,74 +948,63 @@ struct SweepArgs {
   int32_t query;      // index of the query in the batch
   int64_t sweep_docs; // documents per wave, multiple of the skip block
   int32_t n_groups;   // workgroups
-  int32_t doc_tile;
-  int32_t ecap;       // cursor slots per wave
+  int32_t acc_bytes;  // bytes of the first LDS region
+  int32_t ecap;       // entry slots
+  int32_t pcap;       // member slots
 };
 
-template <int W, int KPL, typename ST>
+template <int W, int RS, int KPL, typename ST>
 __global__ __launch_bounds__(W * 64) void k_sweep(SweepArgs a) {
   constexpr int KP = KPL * 64;
+  constexpr int DT = 64 * RS;
   extern __shared__ __align__(16) uint8_t smem[];
-  const int DT = a.doc_tile;
   const int w = threadIdx.x >> 6;
   const int l = lane();
-  float* acc = reinterpret_cast<float*>(smem) + (size_t)w * DT;
-  int32_t* cursor = reinterpret_cast<int32_t*>(smem + (size_t)W * DT * 4) + (size_t)w * a.ecap;
+  float* acc_sp = reinterpret_cast<float*>(smem) + (size_t)w * DT;
+  uint8_t* sbase = smem + a.acc_bytes;
+  const EntryState st = carve_state(sbase, a.ecap, W, w);
+  int32_t* mem_lds = reinterpret_cast<int32_t*>(
+      sbase + (size_t)a.ecap * (kEntryStaticBytes + (size_t)W * kEntryDynBytes));
   const IndexView& ix = a.ix;
   const BatchView& bv = a.bv;
-  const typename ST::T* data = reinterpret_cast<const typename ST::T*>(ix.data);
   const int q = a.query;
   const int64_t e_base = bv.tile_e0[q];
   const int E = bv.wave_e0[(int64_t)q * 2 + 1];
+  const int64_t p0 = bv.q_off[q];
+  const int P = (int)(bv.q_off[q + 1] - p0);
+  const DenseEntry* dent = bv.dense_ent + p0;
+  const int n_dense = bv.dense_n[q];
   const int64_t sw = (int64_t)blockIdx.x * W + w;
   const int64_t d_lo = sw * a.sweep_docs;
   const int64_t d_hi = (d_lo + a.sweep_docs < ix.n_docs) ? d_lo + a.sweep_docs : ix.n_docs;
   const int cap = bv.q_k[q];
 
-  for (int e = 0; e < E; ++e) {
-    const Entry en = bv.entries[e_base + e];
-    const int64_t c = (d_lo < d_hi) ? find_cursor(ix, en, d_lo) : 0;
-    if (l == 0) cursor[e] = (int32_t)c;
-  }
+  for (int i = threadIdx.x; i < P; i += W * 64) mem_lds[i] = bv.members[p0 + i];
+  if (w == 0) load_static(bv.entries + e_base, 0, E, p0, st);
+  __syncthreads();
+  if (d_lo < d_hi) init_cursors(ix, 0, E, d_lo, st);
   for (int i = l; i < DT / 4; i += 64)
-    reinterpret_cast<float4*>(acc)[i] = make_float4(0.f, 0.f, 0.f, 0.f);
+    reinterpret_cast<float4*>(acc_sp)[i] = make_float4(0.f, 0.f, 0.f, 0.f);
+  float acc[1][RS];
+#pragma unroll
+  for (int r = 0; r < RS; ++r) acc[0][r] = 0.f;
   TopList<KPL> L;
   L.clear();
   uint64_t thr = 0;
+  float thr_s = -INFINITY;
 
   for (int64_t t0 = d_lo; t0 < d_hi; t0 += DT) {
     const int64_t t1 = (t0 + DT < d_hi) ? t0 + DT : d_hi;
-    const int32_t t1i = (int32_t)t1;
-    for (int e = 0; e < E; ++e) {
-      const Entry en = bv.entries[e_base + e];
-      const int64_t len = en.row_hi - en.row_lo;
-      const float mult = (float)((uint32_t)bv.members[en.mem_off] >> 16);
-      int64_t c = cursor[e];
-      while (true) {
-        const int64_t off = c + l;
-        const bool in_row = off < len;
-        const int32_t d = in_row ? ix.indices[en.row_lo + off] : INT32_MAX;
-        const bool v = d < t1i && d >= (int32_t)t0;
-        if (v) acc[d - (int32_t)t0] += ST::load(data, en.row_lo + off) * mult;
-        const int n = __popcll(ballot(v));
-        c += n;
-        if (n < 64) break;
-      }
-      if (l == 0) cursor[e] = (int32_t)c;
-    }
-    float4* row = reinterpret_cast<float4*>(acc);
-    for (int i = l; i < DT / 4; i += 64) {
-      const float4 v4 = row[i];
-      row[i] = make_float4(0.f, 0.f, 0.f, 0.f);
-      const int64_t db = t0 + 4 * i;
-      const float vs[4] = {v4.x, v4.y, v4.z, v4.w};
+    accumulate_tile<ST>(ix, st, 0, E, mem_lds, acc_sp, DT, t0, t1);
+    accumulate_dense<ST, 1, RS>(ix, dent, n_dense, t0 + l * RS, acc);
+    float v[RS];
+    take_lds<RS>(acc_sp + l * RS, v);
 #pragma unroll
-      for (int c = 0; c < 4; ++c) {
-        const int64_t doc = db + c;
-        const uint64_t key = (doc < t1) ? make_key(vs[c], (uint32_t)doc) : 0ull;
-        L.offer(key, cap, thr);
-      }
+    for (int r = 0; r < RS; ++r) {
+      v[r] += acc[0][r];
+      acc[0][r] = 0.f;
     }
+    select_regs<KPL, RS>(v, t0 + l * RS, t1, L, cap, thr, thr_s);
   }
   // merge the W lists of the workgroup (the accumulator region is reused)
   __syncthreads();

@@ -127,26 +127,51 @@ def test_scaled_corpus_many_tiles_and_groups(form, k):
 
 
 def test_batched_shapes_agree():
-    """Every launch shape the autotuner may pick gives results within tolerance."""
+    """Every built launch shape, with and without the dense head rows, gives results within
+    tolerance; invalid shapes are rejected."""
     import torch
+    from paper_2407_03618_amd import BM25Error
     c = make_corpus(2, n_docs=60_000)
     q = make_queries(2, n_queries=90, vocab=c.vocab, k=50)
     ref = eager.build_index(c.tokens, c.doc_offsets, c.vocab, token_subset=np.unique(q.q_ids))
     idx = _index(c, dtype="f32")
-    from paper_2407_03618_amd import BM25Error
-    for waves in (4, 8):
-        for qpw in (1, 2, 4):
-            for dt, g in ((512, 8), (1024, 16), (2048, 3)):
-                idx.set_plan(dict(q_tile=waves * qpw, waves=waves, doc_tile=dt, doc_groups=g))
-                if waves * qpw * dt * 4 > 150 * 1024:  # accumulators alone exceed the LDS
-                    with pytest.raises(BM25Error) as e:
-                        _run(idx, q, 50, "batch")
-                    assert e.value.code == -1
-                    continue
+    for waves, dt in ((8, 1024), (4, 1024), (8, 2048)):
+        for qt in (waves, 2 * waves, 4 * waves):
+            if qt == 4 * waves and waves * dt // (64 * waves) > 16:
+                continue
+            for g, sparse_only in ((8, 0), (3, 1), (16, 0)):
+                plan = dict(q_tile=qt, waves=waves, doc_tile=dt, doc_groups=g,
+                            sparse_only=sparse_only)
+                idx.set_plan(plan)
                 ids, sc, cnt = _run(idx, q, 50, "batch")
-                check_batch(ref, q.q_ids, q.q_offsets, q.k, ids, sc, cnt, 1e-5,
-                            f"W={waves} QPW={qpw} DT={dt} G={g}", sample=range(0, q.n, 3))
+                check_batch(ref, q.q_ids, q.q_offsets, q.k, ids, sc, cnt, 1e-5, str(plan),
+                            sample=range(0, q.n, 3))
+    for bad in (dict(q_tile=16, waves=8, doc_tile=512, doc_groups=8),
+                dict(q_tile=12, waves=8, doc_tile=1024, doc_groups=8),
+                dict(q_tile=4, waves=8, doc_tile=1024, doc_groups=8),
+                dict(q_tile=16, waves=2, doc_tile=1024, doc_groups=8)):
+        with pytest.raises(BM25Error) as e:
+            idx.set_plan(bad)
+        assert e.value.code == -1
     idx.set_plan(None)
     best = idx.autotune(_dev(q.q_ids), q.q_offsets, 50, 50)
     assert best["q_tile"] >= 1
+    ids, sc, cnt = _run(idx, q, 50, "batch")
+    check_batch(ref, q.q_ids, q.q_offsets, q.k, ids, sc, cnt, 1e-5, "tuned")
+    torch.cuda.synchronize()
+
+
+@pytest.mark.parametrize("form", ["batch", "plain"])
+def test_sparse_only_matches_dense_path(form):
+    """The dense copies of the head rows and the sparse rows give the same top-k."""
+    import torch
+    c = make_corpus(0)
+    q = make_queries(0)
+    ref = eager.build_index(c.tokens, c.doc_offsets, c.vocab)
+    idx = _index(c, dtype="f32")
+    plan = idx.get_plan(q.n, int(np.diff(q.q_offsets).max()), 10)
+    plan["sparse_only"] = 1
+    idx.set_plan(plan)
+    ids, sc, cnt = _run(idx, q, 10, form)
+    check_batch(ref, q.q_ids, q.q_offsets, q.k, ids, sc, cnt, 1e-5, f"sparse-only {form}")
     torch.cuda.synchronize()
