@@ -169,7 +169,11 @@ int bm25_search_plain(const bm25_index* index, const int32_t* q_ids, const int64
  *   waves       wavefronts per workgroup (1..16)
  *   doc_tile    documents per LDS accumulator tile (multiple of 256)
  *   doc_groups  document ranges the corpus is split into; a workgroup owns one (tile, range)
- *   use_graph   1: replay the launch sequence from a captured hipGraph
+ *   query_order 0: automatic (grouped when the index has dense rows and q_tile times the
+ *               longest query fits one tile's position capacity of 4080); 1: grouped, under
+ *               the same conditions; 2: as given. Grouped: the batch is permuted on the
+ *               device so that queries holding the same frequent tokens share query tiles;
+ *               results are still written in the caller's order
  *   sparse_only 1: read every token from the sparse rows, ignoring the dense copies of the most
  *               frequent tokens' rows (same results within rounding; for testing)
  * Built shapes: waves 8 with doc_tile 1024 (2 documents per lane) or 2048 (4 per lane), waves 4
@@ -180,7 +184,7 @@ typedef struct {
   int32_t waves;
   int32_t doc_tile;
   int32_t doc_groups;
-  int32_t use_graph;
+  int32_t query_order;
   int32_t sparse_only;
 } bm25_tile_plan;
 

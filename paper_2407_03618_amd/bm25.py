@@ -44,7 +44,7 @@ class Params(ctypes.Structure):
 class TilePlan(ctypes.Structure):
     _fields_ = [("q_tile", ctypes.c_int32), ("waves", ctypes.c_int32),
                 ("doc_tile", ctypes.c_int32), ("doc_groups", ctypes.c_int32),
-                ("use_graph", ctypes.c_int32), ("sparse_only", ctypes.c_int32)]
+                ("query_order", ctypes.c_int32), ("sparse_only", ctypes.c_int32)]
 
     def as_dict(self):
         return {f: int(getattr(self, f)) for f, _ in self._fields_}
@@ -261,7 +261,7 @@ class Index:
             return
         p = TilePlan(int(plan.get("q_tile", 0)), int(plan.get("waves", 0)),
                      int(plan.get("doc_tile", 0)), int(plan.get("doc_groups", 0)),
-                     int(plan.get("use_graph", 0)), int(plan.get("sparse_only", 0)))
+                     int(plan.get("query_order", 0)), int(plan.get("sparse_only", 0)))
         _check(L.bm25_search_set_plan(self._h, ctypes.byref(p)))
 
     def get_plan(self, n_queries: int, max_query_len: int, k_max: int) -> dict:

@@ -694,6 +694,12 @@ extern "C" int bm25_index_build(const int32_t* token_ids, int64_t n_tokens,
     std::sort(toks.begin(), toks.end());
     for (size_t h = 0; h < toks.size(); ++h) did[toks[h]] = (int32_t)h;
     idx->n_dense = (int64_t)toks.size();
+    // rank of each row by document frequency, for grouping queries that share frequent rows
+    std::vector<int32_t> rank(std::max<size_t>(toks.size(), 1), 0);
+    for (size_t r = 0; r < cand.size(); ++r) rank[(size_t)did[cand[r].second]] = (int32_t)r;
+    BM25_ALLOC(idx->dense_rank, rank.size() * 4);
+    BM25_HIP(hipMemcpyAsync(idx->dense_rank.ptr, rank.data(), rank.size() * 4,
+                            hipMemcpyHostToDevice, s));
     BM25_ALLOC(idx->dense_id, (size_t)V * 4);
     BM25_HIP(hipMemcpyAsync(idx->dense_id.ptr, did.data(), (size_t)V * 4, hipMemcpyHostToDevice,
                             s));
@@ -759,13 +765,14 @@ extern "C" int64_t bm25_index_device_bytes(const bm25_index* index) {
   const bm25::DevBuf* bufs[] = {&index->indptr, &index->indices, &index->tf, &index->data,
                                 &index->df, &index->idf, &index->theta, &index->theta32,
                                 &index->doclen, &index->long_id, &index->skip,
-                                &index->dense_id, &index->dense};
+                                &index->dense_id, &index->dense_rank, &index->dense};
   int64_t total = 0;
   for (auto* b : bufs) total += (int64_t)b->bytes;
   const bm25::SearchScratch* ss[] = {&index->batch_scratch, &index->plain_scratch};
   for (auto* s : ss) {
-    const bm25::DevBuf* sb[] = {&s->meta, &s->wave_e0, &s->qstat, &s->entries, &s->members,
-                                &s->cand};
+    const bm25::DevBuf* sb[] = {&s->meta,      &s->wave_e0, &s->qstat, &s->entries,
+                                &s->members,   &s->cand,    &s->dense_ent, &s->dense_n,
+                                &s->perm,      &s->ids2,    &s->off2,  &s->k2};
     for (auto* b : sb) total += (int64_t)b->bytes;
   }
   return total;

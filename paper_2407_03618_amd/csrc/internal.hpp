@@ -120,6 +120,10 @@ struct SearchScratch {
   DevBuf cand;      // uint64 candidate lists
   DevBuf dense_ent; // planner dense entries (16 B per position)
   DevBuf dense_n;   // int32 per tile
+  DevBuf perm;      // int32[n]: caller's index of each grouped query
+  DevBuf ids2;      // grouped batch: token ids, offsets, k
+  DevBuf off2;
+  DevBuf k2;
   PinnedBuf host;   // staging for the host-side plan
   hipEvent_t host_free = nullptr;  // the staging buffer may be rewritten once this has fired
 };
@@ -129,7 +133,7 @@ struct TileShape {
   int waves = 0;
   int doc_tile = 0;
   int doc_groups = 0;
-  int use_graph = 0;
+  int query_order = 0;  // 0 automatic, 1 grouped by frequent tokens, 2 as given
   int sparse_only = 0;
 };
 
@@ -159,6 +163,7 @@ struct bm25_index {
   int64_t n_long = 0;
   int64_t n_blocks = 0;   // ceil(N / kSkipBlock)
   bm25::DevBuf dense_id;  // int32[V]: dense row of the token, or -1
+  bm25::DevBuf dense_rank;  // int32[n_dense]: rank of the row by document frequency (0 = most)
   bm25::DevBuf dense;     // store dtype[n_dense][n_pad]: S (or S_delta) per document, 0 if absent
   int64_t n_dense = 0;
   int64_t n_pad = 0;      // dense row length: N rounded up to kDensePad

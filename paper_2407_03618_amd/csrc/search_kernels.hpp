@@ -48,6 +48,7 @@ struct IndexView {
   const uint32_t* skip;
   const float* theta32;   // nullptr for sparse variants
   const int32_t* dense_id;  // dense row of each token or -1; nullptr: no dense rows used
+  const int32_t* dense_rank;  // rank of each dense row by document frequency (0 = most)
   const void* dense;      // [n_dense][n_pad] stored scores
   int64_t n_docs;
   int64_t n_blocks;
@@ -169,6 +170,79 @@ struct PlanSmem {
 };
 
 #ifdef BM25_SEARCH_MAIN
+// Query grouping: one workgroup per window of up to kPlanSort consecutive queries. A query's
+// signature has one bit per dense row it holds (the most frequent row in the highest bit); the
+// window is sorted by signature, descending, then by position, so that queries sharing frequent
+// rows fall into the same query tile and that tile reads each shared dense row once. Writes the
+// grouped batch (ids, offsets, k) and perm[grouped index] = caller's index.
+struct ReorderArgs {
+  const int32_t* q_ids;
+  const int64_t* q_off;
+  const int32_t* q_k;
+  const int32_t* dense_id;
+  const int32_t* dense_rank;
+  int32_t vocab;
+  int32_t n;
+  int32_t* ids2;
+  int64_t* off2;
+  int32_t* k2;
+  int32_t* perm;
+};
+
+__global__ __launch_bounds__(kPlanThreads) void k_reorder(ReorderArgs a) {
+  constexpr int kSigBits = 52;  // rows ranked below this share no bit
+  __shared__ uint64_t key[kPlanSort];
+  __shared__ uint32_t len[kPlanSort];
+  __shared__ uint32_t lds4[4];
+  const int tid = threadIdx.x;
+  const int w0 = blockIdx.x * kPlanSort;
+  const int m = (a.n - w0 < kPlanSort) ? a.n - w0 : kPlanSort;
+  int npow = 1;
+  while (npow < m) npow <<= 1;
+  for (int i = tid; i < npow; i += kPlanThreads) {
+    uint64_t k = ~0ull;  // padding sorts last (a real key has a zero bit: i < m <= 4096)
+    if (i < m) {
+      const int q = w0 + i;
+      uint64_t sig = 0;
+      for (int64_t p = a.q_off[q]; p < a.q_off[q + 1]; ++p) {
+        const int32_t t = a.q_ids[p];
+        if (t < 0 || t >= a.vocab) continue;
+        const int32_t h = a.dense_id[t];
+        if (h < 0) continue;
+        const int32_t r = a.dense_rank[h];
+        if (r < kSigBits) sig |= 1ull << (kSigBits - 1 - r);
+      }
+      k = ((~sig & ((1ull << kSigBits) - 1)) << 12) | (uint64_t)i;
+    }
+    key[i] = k;
+  }
+  __syncthreads();
+  lds_bitonic_sort(key, npow);
+  for (int i = tid; i < kPlanSort; i += kPlanThreads) {
+    uint32_t n_i = 0;
+    if (i < m) {
+      const int q = w0 + (int)(key[i] & 0xFFFu);
+      n_i = (uint32_t)(a.q_off[q + 1] - a.q_off[q]);
+      a.perm[w0 + i] = q;
+      a.k2[w0 + i] = a.q_k[q];
+    }
+    len[i] = n_i;
+  }
+  __syncthreads();
+  lds_scan_u32(len, kPlanSort, lds4);
+  const int64_t base = a.q_off[w0];
+  for (int i = tid; i < m; i += kPlanThreads) a.off2[w0 + i] = base + len[i];
+  if (w0 + m == a.n && tid == 0) a.off2[a.n] = a.q_off[a.n];
+  // token ids: one wave per query
+  const int wv = tid >> 6, l = lane();
+  for (int i = wv; i < m; i += kPlanThreads / 64) {
+    const int q = w0 + (int)(key[i] & 0xFFFu);
+    const int64_t src = a.q_off[q], cnt = a.q_off[q + 1] - src;
+    const int64_t dst = base + len[i];
+    for (int64_t j = l; j < cnt; j += 64) a.ids2[dst + j] = a.q_ids[src + j];
+  }
+}
+
 // W: waves of the consuming gather kernel (entries are dealt to them); W == 1 disables splits.
 __global__ __launch_bounds__(kPlanThreads) void k_plan(IndexView ix, BatchView bv, int W) {
   __shared__ PlanSmem sm;
@@ -1041,6 +1115,7 @@ struct MergeArgs {
   int32_t* out_ids;
   float* out_scores;
   int32_t* out_count;
+  const int32_t* perm;    // output row of each query, or nullptr for the identity
   int64_t n_docs;
   int32_t lists;
   int32_t k_max;
@@ -1091,8 +1166,9 @@ __global__ __launch_bounds__(256) void k_merge(MergeArgs a) {
     shift = part;
   }
   const int64_t count = bad ? 0 : ((int64_t)cap < a.n_docs ? cap : a.n_docs);
-  int32_t* oid = a.out_ids + (int64_t)q * a.k_max;
-  float* osc = a.out_scores + (int64_t)q * a.k_max;
+  const int64_t row = a.perm ? a.perm[q] : q;
+  int32_t* oid = a.out_ids + row * a.k_max;
+  float* osc = a.out_scores + row * a.k_max;
   for (int r0 = 0; r0 < a.k_max; r0 += 64) {
     const int r = r0 + l;
     const int i = r0 >> 6;
@@ -1110,7 +1186,7 @@ __global__ __launch_bounds__(256) void k_merge(MergeArgs a) {
       }
     }
   }
-  if (l == 0) a.out_count[q] = bad ? -2 : (int32_t)count;
+  if (l == 0) a.out_count[row] = bad ? -2 : (int32_t)count;
 }
 
 }  // namespace bm25dev

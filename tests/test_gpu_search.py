@@ -175,3 +175,52 @@ def test_sparse_only_matches_dense_path(form):
     ids, sc, cnt = _run(idx, q, 10, form)
     check_batch(ref, q.q_ids, q.q_offsets, q.k, ids, sc, cnt, 1e-5, f"sparse-only {form}")
     torch.cuda.synchronize()
+
+
+def test_query_order_grouped_matches_given():
+    """Grouping the batch by frequent tokens (two sort windows, a ragged last tile, per-query k,
+    an empty query, invalid ids) returns every query's own results in the caller's order; a
+    batch whose longest query does not fit a grouped tile falls back to the given order."""
+    import torch
+    c = make_corpus(2, n_docs=60_000)
+    q = make_queries(2, n_queries=4096 + 333, vocab=c.vocab, k=40)
+    rng = np.random.default_rng(5)
+    q.k[:] = rng.integers(1, 41, q.n).astype(np.int32)
+    lens = np.diff(q.q_offsets)
+    # query 7 empty; queries 11 and 4200 hold an id outside the vocabulary
+    parts = [q.query(i) for i in range(q.n)]
+    parts[7] = parts[7][:0]
+    parts[11] = np.concatenate([parts[11], [c.vocab + 3]]).astype(np.int32)
+    parts[4200] = np.concatenate([[-5], parts[4200]]).astype(np.int32)
+    q_ids = np.concatenate(parts).astype(np.int32)
+    q_off = np.zeros(q.n + 1, np.int64)
+    q_off[1:] = np.cumsum([len(p) for p in parts])
+    qb = QueryBatch(q_ids, q_off, q.k)
+    ok_ids = q_ids[(q_ids >= 0) & (q_ids < c.vocab)]
+    ref = eager.build_index(c.tokens, c.doc_offsets, c.vocab, token_subset=np.unique(ok_ids))
+    idx = _index(c, dtype="f16")
+    sample = [i for i in range(0, q.n, 29) if i not in (11, 4200)] + [7, q.n - 1]
+    out = {}
+    for order in (2, 1):
+        plan = idx.get_plan(q.n, int(lens.max()) + 1, 40)
+        plan["query_order"] = order
+        idx.set_plan(plan)
+        ids, sc, cnt = _run(idx, qb, 40, "batch")
+        assert cnt[11] == -2 and cnt[4200] == -2 and np.all(ids[11] == -1)
+        check_batch(ref, q_ids, q_off, q.k, ids, sc, cnt, RTOL["f16"], f"order {order}",
+                    sample=sample)
+        out[order] = cnt
+    assert np.array_equal(out[1], out[2])
+    # longest query 600 ids: 8 queries per tile exceed the tile's positions, so no grouping
+    long_q = rng.integers(0, c.vocab, 600).astype(np.int32)
+    parts2 = [long_q] + [q.query(i) for i in range(1, 200)]
+    q_ids2 = np.concatenate(parts2).astype(np.int32)
+    q_off2 = np.zeros(201, np.int64)
+    q_off2[1:] = np.cumsum([len(p) for p in parts2])
+    qb2 = QueryBatch(q_ids2, q_off2, np.full(200, 40, np.int32))
+    ref2 = eager.build_index(c.tokens, c.doc_offsets, c.vocab, token_subset=np.unique(q_ids2))
+    idx.set_plan(dict(q_tile=8, waves=4, doc_tile=1024, doc_groups=8, query_order=1))
+    ids, sc, cnt = _run(idx, qb2, 40, "batch")
+    check_batch(ref2, q_ids2, q_off2, qb2.k, ids, sc, cnt, RTOL["f16"], "long query",
+                sample=range(0, 200, 7))
+    torch.cuda.synchronize()
