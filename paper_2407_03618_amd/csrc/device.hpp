@@ -211,4 +211,59 @@ struct TopList {
   }
 };
 
+// A TopList fed through a staging register: keys above the list's threshold are compacted
+// into one staged key per lane and merged 64 at a time, so a key that enters costs a few
+// instructions instead of a full insertion. The threshold is refreshed at each merge; until
+// then it may lag, which only lets more keys into the stage. Whole-wave, uniform calls.
+template <int KPL>
+struct StagedTopList {
+  TopList<KPL> L;
+  uint64_t b;    // this lane's staged key (lanes < n)
+  int n;         // staged keys
+  int cap;       // list positions that count (k)
+  uint64_t thr;  // key at position cap-1 after the last merge (0 while fewer than cap keys)
+
+  __device__ __forceinline__ void init(int k) {
+    L.clear();
+    b = 0;
+    n = 0;
+    cap = k;
+    thr = 0;
+  }
+
+  __device__ __forceinline__ float thr_score() const {
+    return (thr == 0) ? -INFINITY : key_score(thr);
+  }
+
+  __device__ __forceinline__ void flush() {
+    if (n == 0) return;
+    L.merge_chunk(lane() < n ? b : 0ull);
+    n = 0;
+    thr = L.at(cap - 1);
+  }
+
+  // Offers one key per lane (0: none).
+  __device__ __forceinline__ void offer(uint64_t key) {
+    bool p = key > thr;
+    uint64_t m = ballot(p);
+    if (m == 0) return;
+    int c = __popcll(m);
+    if (n + c > 64) {
+      flush();
+      p = key > thr;
+      m = ballot(p);
+      if (m == 0) return;
+      c = __popcll(m);
+    }
+    const int l = lane();
+    const int rp = __popcll(m & lanemask_lt());
+    // passing lanes go to n.., the others fill the remaining lanes (a permutation of 0..63)
+    const int dest = p ? (n + rp) : ((n + c + (l - rp)) & 63);
+    const uint32_t lo = (uint32_t)__builtin_amdgcn_ds_permute(dest << 2, (int)(uint32_t)key);
+    const uint32_t hi = (uint32_t)__builtin_amdgcn_ds_permute(dest << 2, (int)(uint32_t)(key >> 32));
+    if (l >= n && l < n + c) b = ((uint64_t)hi << 32) | lo;
+    n += c;
+  }
+};
+
 }  // namespace bm25dev

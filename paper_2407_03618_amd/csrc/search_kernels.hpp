@@ -869,8 +869,7 @@ __device__ __forceinline__ void fold_lds(float* p, float* v) {
 // below t1) to the wave's list when any of them reaches the list's k-th score.
 template <int KPL, int R>
 __device__ __forceinline__ void select_regs(const float* v, int64_t first, int64_t t1,
-                                            TopList<KPL>& L, int cap, uint64_t& thr,
-                                            float& thr_s) {
+                                            StagedTopList<KPL>& S, float& thr_s) {
   bool p = false;
 #pragma unroll
   for (int r = 0; r < R; ++r) p |= v[r] >= thr_s;
@@ -878,10 +877,9 @@ __device__ __forceinline__ void select_regs(const float* v, int64_t first, int64
 #pragma unroll
     for (int r = 0; r < R; ++r) {
       const int64_t doc = first + r;
-      const uint64_t key = (doc < t1) ? make_key(v[r], (uint32_t)doc) : 0ull;
-      L.offer(key, cap, thr);
+      S.offer((doc < t1 && v[r] >= thr_s) ? make_key(v[r], (uint32_t)doc) : 0ull);
     }
-    thr_s = (thr == 0) ? -INFINITY : key_score(thr);
+    thr_s = S.thr_score();
   }
 }
 
@@ -1062,9 +1060,8 @@ __global__ __launch_bounds__(W * 64) void k_sweep(SweepArgs a) {
   float acc[1][RS];
 #pragma unroll
   for (int r = 0; r < RS; ++r) acc[0][r] = 0.f;
-  TopList<KPL> L;
-  L.clear();
-  uint64_t thr = 0;
+  StagedTopList<KPL> S;
+  S.init(cap);
   float thr_s = -INFINITY;
 
   for (int64_t t0 = d_lo; t0 < d_hi; t0 += DT) {
@@ -1078,8 +1075,11 @@ __global__ __launch_bounds__(W * 64) void k_sweep(SweepArgs a) {
       v[r] += acc[0][r];
       acc[0][r] = 0.f;
     }
-    select_regs<KPL, RS>(v, t0 + l * RS, t1, L, cap, thr, thr_s);
+    select_regs<KPL, RS>(v, t0 + l * RS, t1, S, thr_s);
   }
+  S.flush();
+  TopList<KPL>& L = S.L;
+  uint64_t thr = S.thr;
   // merge the W lists of the workgroup (the accumulator region is reused)
   __syncthreads();
   uint64_t* sh = reinterpret_cast<uint64_t*>(smem);
