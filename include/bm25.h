@@ -213,10 +213,12 @@ int bm25_kernel_time_read(bm25_index* index, double* total_ms, int64_t* launches
  * Serving: continuous batching (Section 2, "Multi-threading", carried to a GPU request loop).
  *
  * The server keeps the index resident and runs a scheduler thread. Submitted queries wait in a
- * host queue; whenever a device slot frees up, the scheduler admits every waiting request that
- * fits the slot count and the device accumulator budget into the next micro-batch and launches
+ * host queue; whenever a device slot frees up, the scheduler admits the waiting requests that
+ * fit the slot count and the device accumulator budget into the next micro-batch and launches
  * it on one of n_streams streams, so micro-batches overlap on the device while later requests
- * keep arriving. Results are copied to pinned host memory and handed out by bm25_serve_poll.
+ * keep arriving. A micro-batch holds one list-size class (k rounded up to a power of two, at
+ * least 64): the oldest waiting request's, with the waiting requests of that class behind it.
+ * Results are copied to pinned host memory and handed out by bm25_serve_poll.
  *
  * config: hbm_budget_bytes  device bytes the server may use for per-batch scratch (> 0)
  *         max_slots         requests in flight (queued + on the device), 1..1<<20

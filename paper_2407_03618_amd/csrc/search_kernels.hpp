@@ -841,6 +841,30 @@ __device__ __forceinline__ void select_row(float* rowp, int DT, int64_t t0, int6
   }
 }
 
+// The same filter feeding a staged list (long lists, where one insertion per key is costly).
+template <int KPL>
+__device__ __forceinline__ void select_row(float* rowp, int DT, int64_t t0, int64_t t1,
+                                           StagedTopList<KPL>& S) {
+  const int l = lane();
+  float4* row = reinterpret_cast<float4*>(rowp);
+  float thr_s = S.thr_score();
+  for (int i = l; i < DT / 4; i += 64) {
+    const float4 v4 = row[i];
+    row[i] = make_float4(0.f, 0.f, 0.f, 0.f);
+    const bool p = (v4.x >= thr_s) || (v4.y >= thr_s) || (v4.z >= thr_s) || (v4.w >= thr_s);
+    if (ballot(p)) {
+      const int64_t db = t0 + 4 * i;
+      const float vs[4] = {v4.x, v4.y, v4.z, v4.w};
+#pragma unroll
+      for (int c = 0; c < 4; ++c) {
+        const int64_t doc = db + c;
+        S.offer((doc < t1 && vs[c] >= thr_s) ? make_key(vs[c], (uint32_t)doc) : 0ull);
+      }
+      thr_s = S.thr_score();
+    }
+  }
+}
+
 // Adds R register values into an LDS row (the lane owns these documents) and clears them.
 template <int R>
 __device__ __forceinline__ void fold_lds(float* p, float* v) {
@@ -963,15 +987,23 @@ __global__ __launch_bounds__(W * 64) void k_gather(GatherArgs a) {
   for (int q = 0; q < QT; ++q)
 #pragma unroll
     for (int r = 0; r < R; ++r) acc[q][r] = 0.f;
-  TopList<KPL> L[QPW];
-  uint64_t thr[QPW];
-  int cap[QPW];
+  // lists of 256 keys and more take their candidates through a staging register
+  constexpr bool kStaged = KPL >= 4;
+  TopList<KPL> L[kStaged ? 1 : QPW];
+  uint64_t thr[kStaged ? 1 : QPW];
+  int cap[kStaged ? 1 : QPW];
+  StagedTopList<KPL> S[kStaged ? QPW : 1];
 #pragma unroll
   for (int j = 0; j < QPW; ++j) {
-    L[j].clear();
-    thr[j] = 0;
     const int ql = w * QPW + j;
-    cap[j] = (ql < nq) ? bv.q_k[q0 + ql] : 1;
+    const int k = (ql < nq) ? bv.q_k[q0 + ql] : 1;
+    if constexpr (kStaged) {
+      S[j].init(k);
+    } else {
+      L[j].clear();
+      thr[j] = 0;
+      cap[j] = k;
+    }
   }
   __syncthreads();
   const int first = w * 64 * R + l * R;
@@ -990,7 +1022,12 @@ __global__ __launch_bounds__(W * 64) void k_gather(GatherArgs a) {
 #pragma unroll
     for (int j = 0; j < QPW; ++j) {
       const int ql = w * QPW + j;
-      if (ql < nq) select_row<KPL>(rows + ql * DT, DT, t0, t1, L[j], cap[j], thr[j]);
+      if (ql < nq) {
+        if constexpr (kStaged)
+          select_row<KPL>(rows + ql * DT, DT, t0, t1, S[j]);
+        else
+          select_row<KPL>(rows + ql * DT, DT, t0, t1, L[j], cap[j], thr[j]);
+      }
     }
     __syncthreads();
   }
@@ -999,8 +1036,14 @@ __global__ __launch_bounds__(W * 64) void k_gather(GatherArgs a) {
     const int ql = w * QPW + j;
     if (ql < nq) {
       uint64_t* out = a.cand + ((int64_t)(q0 + ql) * a.n_groups + group) * KP;
+      if constexpr (kStaged) {
+        S[j].flush();
 #pragma unroll
-      for (int i = 0; i < KPL; ++i) out[l + 64 * i] = L[j].e[i];
+        for (int i = 0; i < KPL; ++i) out[l + 64 * i] = S[j].L.e[i];
+      } else {
+#pragma unroll
+        for (int i = 0; i < KPL; ++i) out[l + 64 * i] = L[j].e[i];
+      }
     }
   }
 }

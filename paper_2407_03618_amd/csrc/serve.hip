@@ -205,14 +205,26 @@ static void scheduler(bm25_server* sv) {
       for (auto& lp : sv->lanes) {
         Lane& ln = *lp;
         if (ln.busy || sv->waiting.empty()) continue;
+        // one list-size class per micro-batch (the oldest request's), so that short lists do
+        // not run with the list registers of the longest k; later requests of other classes
+        // keep their order for the next micro-batch
         int64_t bytes = 0;
-        while (!sv->waiting.empty() && (int32_t)ln.batch.size() < sv->cfg.max_batch) {
-          const Request& r = sv->waiting.front();
-          const int64_t b = request_bytes(sv, (int64_t)r.ids.size(), r.k);
+        const int64_t cls = kp_for(sv->waiting.front().k);
+        const size_t window = (size_t)sv->cfg.max_batch * 4;
+        size_t scanned = 0;
+        auto it = sv->waiting.begin();
+        while (it != sv->waiting.end() && scanned < window &&
+               (int32_t)ln.batch.size() < sv->cfg.max_batch) {
+          ++scanned;
+          if (kp_for(it->k) != cls) {
+            ++it;
+            continue;
+          }
+          const int64_t b = request_bytes(sv, (int64_t)it->ids.size(), it->k);
           if (sv->budget_used + bytes + b > sv->cfg.hbm_budget_bytes) break;
           bytes += b;
-          ln.batch.push_back(std::move(sv->waiting.front()));
-          sv->waiting.pop_front();
+          ln.batch.push_back(std::move(*it));
+          it = sv->waiting.erase(it);
         }
         if (ln.batch.empty()) break;  // budget exhausted: wait for a lane to finish
         ln.busy = true;
