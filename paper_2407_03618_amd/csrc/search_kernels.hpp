@@ -1208,6 +1208,19 @@ __global__ __launch_bounds__(256) void k_merge(MergeArgs a) {
     for (int o = 32; o > 0; o >>= 1) part += __shfl_xor(part, o);
     shift = part;
   }
+  if (shift != 0.f) {
+    // Returned scores are (sum of S_delta) + shift rounded to FP32, and the rounding can make
+    // two different sums equal: re-rank by the returned value, then document id, the order the
+    // results promise.
+    TopList<KPL> R;
+    R.clear();
+#pragma unroll
+    for (int i = 0; i < KPL; ++i) {
+      const uint64_t k0 = L.e[i];
+      R.merge_chunk(k0 != 0 ? make_key(key_score(k0) + shift, key_doc(k0)) : 0ull);
+    }
+    L = R;
+  }
   const int64_t count = bad ? 0 : ((int64_t)cap < a.n_docs ? cap : a.n_docs);
   const int64_t row = a.perm ? a.perm[q] : q;
   int32_t* oid = a.out_ids + row * a.k_max;
@@ -1222,7 +1235,7 @@ __global__ __launch_bounds__(256) void k_merge(MergeArgs a) {
     if (r < a.k_max) {
       if (r < count && key != 0) {
         oid[r] = (int32_t)key_doc(key);
-        osc[r] = key_score(key) + shift;
+        osc[r] = key_score(key);
       } else {
         oid[r] = -1;
         osc[r] = -INFINITY;
