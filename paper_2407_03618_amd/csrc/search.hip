@@ -370,8 +370,15 @@ int search_batch_impl(bm25_index* idx, const int32_t* q_ids, const int64_t* q_of
     ra.off2 = sc.off2.as<int64_t>();
     ra.k2 = sc.k2.as<int32_t>();
     ra.perm = sc.perm.as<int32_t>();
+    static bool reorder_lds = false;  // the kernel takes more than the default 64 KB of LDS
+    if (!reorder_lds) {
+      BM25_HIP(hipFuncSetAttribute((const void*)k_reorder,
+                                   hipFuncAttributeMaxDynamicSharedMemorySize,
+                                   (int)kReorderLds));
+      reorder_lds = true;
+    }
     hipLaunchKernelGGL(k_reorder, dim3((unsigned)((n + kPlanSort - 1) / kPlanSort)),
-                       dim3(kPlanThreads), 0, s, ra);
+                       dim3(kPlanThreads), kReorderLds, s, ra);
     BM25_HIP(hipGetLastError());
     b_ids = ra.ids2;
     b_off = ra.off2;

@@ -189,57 +189,76 @@ struct ReorderArgs {
   int32_t* perm;
 };
 
+// LDS: sort keys [kPlanSort] u64 | grouped offsets [kPlanSort + 1] u32 | caller's offsets
+//      [kPlanSort + 1] u32 | scan scratch [4] u32 (all window-relative).
+constexpr size_t kReorderLds = (size_t)kPlanSort * 8 + 2 * ((size_t)kPlanSort + 1) * 4 + 16;
+
 __global__ __launch_bounds__(kPlanThreads) void k_reorder(ReorderArgs a) {
   constexpr int kSigBits = 52;  // rows ranked below this share no bit
-  __shared__ uint64_t key[kPlanSort];
-  __shared__ uint32_t len[kPlanSort];
-  __shared__ uint32_t lds4[4];
+  extern __shared__ __align__(16) uint8_t smem[];
+  uint64_t* key = reinterpret_cast<uint64_t*>(smem);
+  uint32_t* len = reinterpret_cast<uint32_t*>(key + kPlanSort);
+  uint32_t* qoff = len + kPlanSort + 1;
+  uint32_t* lds4 = qoff + kPlanSort + 1;
   const int tid = threadIdx.x;
   const int w0 = blockIdx.x * kPlanSort;
   const int m = (a.n - w0 < kPlanSort) ? a.n - w0 : kPlanSort;
   int npow = 1;
   while (npow < m) npow <<= 1;
-  for (int i = tid; i < npow; i += kPlanThreads) {
-    uint64_t k = ~0ull;  // padding sorts last (a real key has a zero bit: i < m <= 4096)
-    if (i < m) {
-      const int q = w0 + i;
-      uint64_t sig = 0;
-      for (int64_t p = a.q_off[q]; p < a.q_off[q + 1]; ++p) {
-        const int32_t t = a.q_ids[p];
-        if (t < 0 || t >= a.vocab) continue;
-        const int32_t h = a.dense_id[t];
-        if (h < 0) continue;
-        const int32_t r = a.dense_rank[h];
-        if (r < kSigBits) sig |= 1ull << (kSigBits - 1 - r);
-      }
-      k = ((~sig & ((1ull << kSigBits) - 1)) << 12) | (uint64_t)i;
+  const int64_t base = a.q_off[w0];
+  const int64_t P = a.q_off[w0 + m] - base;  // at most 4096 * BM25_MAX_QUERY_LEN
+  for (int i = tid; i <= m; i += kPlanThreads) qoff[i] = (uint32_t)(a.q_off[w0 + i] - base);
+  for (int i = tid; i < npow; i += kPlanThreads) key[i] = 0;
+  __syncthreads();
+  // signatures, one thread per position: the query holding position p is the last i with
+  // qoff[i] <= p (empty queries hold none)
+  for (int64_t p = tid; p < P; p += kPlanThreads) {
+    const int32_t t = a.q_ids[base + p];
+    if (t < 0 || t >= a.vocab) continue;
+    const int32_t h = a.dense_id[t];
+    if (h < 0) continue;
+    const int32_t r = a.dense_rank[h];
+    if (r >= kSigBits) continue;
+    int lo = 0, hi = m - 1;
+    while (lo < hi) {
+      const int mid = (lo + hi + 1) >> 1;
+      if (qoff[mid] <= (uint32_t)p) lo = mid; else hi = mid - 1;
     }
-    key[i] = k;
+    atomicOr(reinterpret_cast<unsigned long long*>(key + lo),
+             (unsigned long long)(1ull << (kSigBits - 1 - r)));
   }
+  __syncthreads();
+  // sort by signature descending, then position; padding sorts last (a real key has a zero
+  // bit since i < m <= 4096)
+  for (int i = tid; i < npow; i += kPlanThreads)
+    key[i] = (i < m) ? (((~key[i] & ((1ull << kSigBits) - 1)) << 12) | (uint64_t)i) : ~0ull;
   __syncthreads();
   lds_bitonic_sort(key, npow);
   for (int i = tid; i < kPlanSort; i += kPlanThreads) {
     uint32_t n_i = 0;
     if (i < m) {
-      const int q = w0 + (int)(key[i] & 0xFFFu);
-      n_i = (uint32_t)(a.q_off[q + 1] - a.q_off[q]);
-      a.perm[w0 + i] = q;
-      a.k2[w0 + i] = a.q_k[q];
+      const int src = (int)(key[i] & 0xFFFu);
+      n_i = qoff[src + 1] - qoff[src];
+      a.perm[w0 + i] = w0 + src;
+      a.k2[w0 + i] = a.q_k[w0 + src];
     }
     len[i] = n_i;
   }
   __syncthreads();
-  lds_scan_u32(len, kPlanSort, lds4);
-  const int64_t base = a.q_off[w0];
+  lds_scan_u32(len, kPlanSort, lds4);  // exclusive offsets of the grouped queries
+  if (tid == 0) len[m] = (uint32_t)P;
+  __syncthreads();
   for (int i = tid; i < m; i += kPlanThreads) a.off2[w0 + i] = base + len[i];
   if (w0 + m == a.n && tid == 0) a.off2[a.n] = a.q_off[a.n];
-  // token ids: one wave per query
-  const int wv = tid >> 6, l = lane();
-  for (int i = wv; i < m; i += kPlanThreads / 64) {
-    const int q = w0 + (int)(key[i] & 0xFFFu);
-    const int64_t src = a.q_off[q], cnt = a.q_off[q + 1] - src;
-    const int64_t dst = base + len[i];
-    for (int64_t j = l; j < cnt; j += 64) a.ids2[dst + j] = a.q_ids[src + j];
+  // token ids, one thread per grouped position
+  for (int64_t p = tid; p < P; p += kPlanThreads) {
+    int lo = 0, hi = m - 1;
+    while (lo < hi) {
+      const int mid = (lo + hi + 1) >> 1;
+      if (len[mid] <= (uint32_t)p) lo = mid; else hi = mid - 1;
+    }
+    const int src = (int)(key[lo] & 0xFFFu);
+    a.ids2[base + p] = a.q_ids[base + qoff[src] + ((uint32_t)p - len[lo])];
   }
 }
 
