@@ -799,33 +799,37 @@ __device__ __forceinline__ void accumulate_dense(const IndexView& ix, const Dens
                                                  int64_t first, float (&acc)[QT][R]) {
   constexpr int U = (16 / R) > 2 ? (16 / R) : 2;
   const typename ST::T* dense = reinterpret_cast<const typename ST::T*>(ix.dense) + first;
+  // values and (query mask, multiplier) of two groups of U entries: one in use, one loading
   float v[2][U][R];
-  auto load_group = [&](int e0, float (&dst)[U][R]) {
+  uint32_t mk[2][U];
+  float mu[2][U];
+  auto load_group = [&](int e0, float (&dst)[U][R], uint32_t (&m)[U], float (&f)[U]) {
 #pragma unroll
     for (int u = 0; u < U; ++u) {
       const int e = (e0 + u < n) ? e0 + u : n - 1;  // clamped: always a valid row
-      load_dense<ST, R>(dense + (int64_t)de[e].row * ix.n_pad, dst[u]);
+      const DenseEntry d = de[e];                   // one 16-byte scalar load
+      load_dense<ST, R>(dense + (int64_t)d.row * ix.n_pad, dst[u]);
+      m[u] = (e0 + u < n) ? d.qmask : 0u;           // entries past the end add nothing
+      f[u] = d.mult;
     }
   };
   if (n <= 0) return;
-  load_group(0, v[0]);
+  load_group(0, v[0], mk[0], mu[0]);
   for (int e0 = 0; e0 < n; e0 += 2 * U) {
 #pragma unroll
     for (int h = 0; h < 2; ++h) {
       const int eg = e0 + h * U;
       if (eg >= n) break;
-      if (eg + U < n) load_group(eg + U, v[h ^ 1]);
+      if (eg + U < n) load_group(eg + U, v[h ^ 1], mk[h ^ 1], mu[h ^ 1]);
 #pragma unroll
       for (int u = 0; u < U; ++u) {
-        if (eg + u < n) {
-          const uint32_t mask = de[eg + u].qmask;
-          const float mult = de[eg + u].mult;
+        const uint32_t mask = mk[h][u];
+        const float mult = mu[h][u];
 #pragma unroll
-          for (int q = 0; q < QT; ++q) {
-            if ((mask >> q) & 1u) {
+        for (int q = 0; q < QT; ++q) {
+          if ((mask >> q) & 1u) {
 #pragma unroll
-              for (int r = 0; r < R; ++r) acc[q][r] = fmaf(mult, v[h][u][r], acc[q][r]);
-            }
+            for (int r = 0; r < R; ++r) acc[q][r] = fmaf(mult, v[h][u][r], acc[q][r]);
           }
         }
       }
