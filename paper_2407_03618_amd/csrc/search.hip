@@ -3,6 +3,7 @@
 #include <hip/hip_runtime.h>
 
 #include <algorithm>
+#include <atomic>
 #include <chrono>
 #include <cmath>
 #include <cstring>
@@ -370,12 +371,13 @@ int search_batch_impl(bm25_index* idx, const int32_t* q_ids, const int64_t* q_of
     ra.off2 = sc.off2.as<int64_t>();
     ra.k2 = sc.k2.as<int32_t>();
     ra.perm = sc.perm.as<int32_t>();
-    static bool reorder_lds = false;  // the kernel takes more than the default 64 KB of LDS
-    if (!reorder_lds) {
+    // the kernel takes more than the default 64 KB of LDS (setting it twice is harmless)
+    static std::atomic<bool> reorder_lds{false};
+    if (!reorder_lds.load(std::memory_order_acquire)) {
       BM25_HIP(hipFuncSetAttribute((const void*)k_reorder,
                                    hipFuncAttributeMaxDynamicSharedMemorySize,
                                    (int)kReorderLds));
-      reorder_lds = true;
+      reorder_lds.store(true, std::memory_order_release);
     }
     hipLaunchKernelGGL(k_reorder, dim3((unsigned)((n + kPlanSort - 1) / kPlanSort)),
                        dim3(kPlanThreads), kReorderLds, s, ra);

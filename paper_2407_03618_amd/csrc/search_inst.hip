@@ -2,6 +2,8 @@
 // Compiled once per type with -DBM25_ST=F32|F16|BF16 and -DBM25_ST_SUFFIX=f32|f16|bf16.
 #include <hip/hip_runtime.h>
 
+#include <atomic>
+
 #include "search_kernels.hpp"
 
 #ifndef BM25_ST
@@ -17,19 +19,21 @@ using namespace bm25dev;
 
 static constexpr int kMaxLds = 160 * 1024;
 
+// Raises the kernel's dynamic LDS limit once per process (concurrent first calls may both set
+// it, which is harmless).
 template <typename F>
-static hipError_t allow_lds(F fn, bool& done) {
-  if (done) return hipSuccess;
+static hipError_t allow_lds(F fn, std::atomic<bool>& done) {
+  if (done.load(std::memory_order_acquire)) return hipSuccess;
   hipError_t e =
       hipFuncSetAttribute((const void*)fn, hipFuncAttributeMaxDynamicSharedMemorySize, kMaxLds);
-  if (e == hipSuccess) done = true;
+  if (e == hipSuccess) done.store(true, std::memory_order_release);
   return e;
 }
 
 template <int W, int QT, int R, int KPL>
 static hipError_t gather_one(dim3 g, size_t sh, hipStream_t s, const GatherArgs& a) {
   auto fn = k_gather<W, QT, R, KPL, BM25_ST>;
-  static bool attr = false;
+  static std::atomic<bool> attr{false};
   hipError_t e = allow_lds(fn, attr);
   if (e != hipSuccess) return e;
   hipLaunchKernelGGL(fn, g, dim3(W * 64), sh, s, a);
@@ -70,7 +74,7 @@ hipError_t BM25_CAT(launch_gather_, BM25_ST_SUFFIX)(int W, int QT, int R, int KP
 template <int W, int KPL>
 static hipError_t sweep_one(dim3 g, size_t sh, hipStream_t s, const SweepArgs& a) {
   auto fn = k_sweep<W, 16, KPL, BM25_ST>;
-  static bool attr = false;
+  static std::atomic<bool> attr{false};
   hipError_t e = allow_lds(fn, attr);
   if (e != hipSuccess) return e;
   hipLaunchKernelGGL(fn, g, dim3(W * 64), sh, s, a);

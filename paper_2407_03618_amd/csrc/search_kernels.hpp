@@ -1202,9 +1202,18 @@ __global__ __launch_bounds__(256) void k_merge(MergeArgs a) {
   TopList<KPL> L;
   L.clear();
   uint64_t thr = 0;
-  for (int64_t c = w; c < chunks; c += MW) {
-    const uint64_t x = base[c * 64 + l];
-    L.offer(x, cap, thr);
+  // chunks are loaded kMergeAhead at a time so that their loads overlap (most are rejected by
+  // one ballot once the list holds k keys)
+  constexpr int kMergeAhead = KPL >= 8 ? 2 : 8;  // long lists leave few registers
+  for (int64_t c0 = w; c0 < chunks; c0 += (int64_t)MW * kMergeAhead) {
+    uint64_t x[kMergeAhead];
+#pragma unroll
+    for (int u = 0; u < kMergeAhead; ++u) {
+      const int64_t c = c0 + (int64_t)u * MW;
+      x[u] = (c < chunks) ? base[c * 64 + l] : 0ull;
+    }
+#pragma unroll
+    for (int u = 0; u < kMergeAhead; ++u) L.offer(x[u], cap, thr);
   }
   if (w > 0) {
 #pragma unroll
@@ -1235,14 +1244,15 @@ __global__ __launch_bounds__(256) void k_merge(MergeArgs a) {
     // Returned scores are (sum of S_delta) + shift rounded to FP32, and the rounding can make
     // two different sums equal: re-rank by the returned value, then document id, the order the
     // results promise.
-    TopList<KPL> R;
-    R.clear();
+    // (the new keys go through the LDS buffer, free by now, so that one list is live at a time)
 #pragma unroll
     for (int i = 0; i < KPL; ++i) {
       const uint64_t k0 = L.e[i];
-      R.merge_chunk(k0 != 0 ? make_key(key_score(k0) + shift, key_doc(k0)) : 0ull);
+      sh[0][l + 64 * i] = (k0 != 0) ? make_key(key_score(k0) + shift, key_doc(k0)) : 0ull;
     }
-    L = R;
+    L.clear();
+#pragma unroll
+    for (int i = 0; i < KPL; ++i) L.merge_chunk(sh[0][l + 64 * i]);
   }
   const int64_t count = bad ? 0 : ((int64_t)cap < a.n_docs ? cap : a.n_docs);
   const int64_t row = a.perm ? a.perm[q] : q;
