@@ -24,6 +24,8 @@ hipError_t launch_sweep_f16(int, int, dim3, size_t, hipStream_t, const SweepArgs
 hipError_t launch_sweep_bf16(int, int, dim3, size_t, hipStream_t, const SweepArgs&);
 
 static constexpr int64_t kMaxLdsBytes = 160 * 1024;
+// queries of the per-query form whose candidate lists are merged by one launch
+static constexpr int32_t kPlainMergeBatch = 256;
 
 static hipError_t launch_gather(int dtype, int W, int QT, int R, int KPL, dim3 g, size_t sh,
                                 hipStream_t s, const GatherArgs& a) {
@@ -479,7 +481,9 @@ int search_plain_impl(bm25_index* idx, const int32_t* q_ids, const int64_t* q_of
   BM25_RESERVE(sc.members, (size_t)std::max<int64_t>(info.positions, 1) * 4);
   BM25_RESERVE(sc.dense_ent, (size_t)std::max<int64_t>(info.positions, 1) * sizeof(DenseEntry));
   BM25_RESERVE(sc.dense_n, (size_t)n * 4);
-  BM25_RESERVE(sc.cand, (size_t)G * KP * 8);
+  // candidate lists of up to kPlainMergeBatch queries, merged by one launch per batch
+  const int32_t mb = std::min<int32_t>(n, kPlainMergeBatch);
+  BM25_RESERVE(sc.cand, (size_t)mb * G * KP * 8);
   Staged dev;
   rc = upload_plan(sc, s, n, n, q_off, k, k_max, tile_q0, tile_e0, dev);
   if (rc != BM25_OK) return rc;
@@ -525,16 +529,21 @@ int search_plain_impl(bm25_index* idx, const int32_t* q_ids, const int64_t* q_of
   ma.n_docs = idx->n_docs;
   ma.lists = (int32_t)G;
   ma.k_max = k_max;
-  for (int32_t i = 0; i < n; ++i) {
-    sa.query = i;
-    hipEvent_t tb;
-    rc = timed_begin(idx, s, &tb);
-    if (rc != BM25_OK) return rc;
-    BM25_HIP(launch_sweep(idx->params.store_dtype, W, KPL, dim3((unsigned)G), (size_t)lds, s, sa));
-    rc = timed_end(idx, s, tb);
-    if (rc != BM25_OK) return rc;
-    ma.q_first = i;
-    BM25_HIP(launch_merge(KPL, dim3(1), s, ma));
+  for (int32_t i0 = 0; i0 < n; i0 += mb) {
+    const int32_t i1 = std::min<int32_t>(n, i0 + mb);
+    for (int32_t i = i0; i < i1; ++i) {
+      sa.query = i;
+      sa.cand = sc.cand.as<uint64_t>() + (size_t)(i - i0) * G * KP;
+      hipEvent_t tb;
+      rc = timed_begin(idx, s, &tb);
+      if (rc != BM25_OK) return rc;
+      BM25_HIP(
+          launch_sweep(idx->params.store_dtype, W, KPL, dim3((unsigned)G), (size_t)lds, s, sa));
+      rc = timed_end(idx, s, tb);
+      if (rc != BM25_OK) return rc;
+    }
+    ma.q_first = i0;
+    BM25_HIP(launch_merge(KPL, dim3((unsigned)(i1 - i0)), s, ma));
   }
   return BM25_OK;
 }

@@ -1199,11 +1199,21 @@ __global__ __launch_bounds__(256) void k_merge(MergeArgs a) {
   const int cap = a.q_k[q];
   const uint64_t* base = a.cand + (int64_t)blockIdx.x * a.lists * KP;
   const int64_t chunks = (int64_t)a.lists * KPL;
+  __shared__ uint64_t tau_w[MW];
+  // Every list holds distinct documents sorted descending, so the largest k-th key of any one
+  // list is a lower bound of the query's k-th key: keys below it are dropped before the merge.
+  uint64_t tau = 0;
+  for (int64_t j = threadIdx.x; j < a.lists; j += MW * 64) tau = umax64(tau, base[j * KP + cap - 1]);
+#pragma unroll
+  for (int o = 32; o > 0; o >>= 1) tau = umax64(tau, bperm64(tau, l ^ o));
+  if (l == 0) tau_w[w] = tau;
+  __syncthreads();
+  tau = umax64(umax64(tau_w[0], tau_w[1]), umax64(tau_w[2], tau_w[3]));
   TopList<KPL> L;
   L.clear();
   uint64_t thr = 0;
   // chunks are loaded kMergeAhead at a time so that their loads overlap (most are rejected by
-  // one ballot once the list holds k keys)
+  // one ballot)
   constexpr int kMergeAhead = KPL >= 8 ? 2 : 8;  // long lists leave few registers
   for (int64_t c0 = w; c0 < chunks; c0 += (int64_t)MW * kMergeAhead) {
     uint64_t x[kMergeAhead];
@@ -1213,7 +1223,7 @@ __global__ __launch_bounds__(256) void k_merge(MergeArgs a) {
       x[u] = (c < chunks) ? base[c * 64 + l] : 0ull;
     }
 #pragma unroll
-    for (int u = 0; u < kMergeAhead; ++u) L.offer(x[u], cap, thr);
+    for (int u = 0; u < kMergeAhead; ++u) L.offer(x[u] >= tau ? x[u] : 0ull, cap, thr);
   }
   if (w > 0) {
 #pragma unroll
