@@ -154,7 +154,8 @@ void bm25_index_free(bm25_index* index);
  * reads, accumulated in LDS-resident FP32 tiles and reduced to top-k inside one persistent
  * kernel per batch (launch shape from the autotuner or bm25_search_set_plan).
  * bm25_search_plain runs the per-query form: each query is one launch that sweeps all
- * documents for that query alone; one small merge launch per 256 queries then ranks each
+ * documents for that query alone (about 2048 one-wave workgroups, each over a contiguous range
+ * of whole 1024-document blocks); one small merge launch per up to 256 queries then ranks each
  * query's candidate lists.
  */
 int bm25_search_batch(const bm25_index* index, const int32_t* q_ids, const int64_t* q_offsets,

@@ -26,6 +26,7 @@ hipError_t launch_sweep_bf16(int, int, dim3, size_t, hipStream_t, const SweepArg
 static constexpr int64_t kMaxLdsBytes = 160 * 1024;
 // queries of the per-query form whose candidate lists are merged by one launch
 static constexpr int32_t kPlainMergeBatch = 256;
+static constexpr int64_t kPlainCandBytes = 512ll << 20;
 
 static hipError_t launch_gather(int dtype, int W, int QT, int R, int KPL, dim3 g, size_t sh,
                                 hipStream_t s, const GatherArgs& a) {
@@ -449,7 +450,7 @@ int search_plain_impl(bm25_index* idx, const int32_t* q_ids, const int64_t* q_of
   if (rc != BM25_OK || n == 0) return rc;
   SearchScratch& sc = idx->plain_scratch;
   const int KPL = kpl_for(k_max), KP = 64 * KPL;
-  const int W = 8;
+  const int W = 1;  // one-wave workgroups: a query's sweepers spread over every CU
   const int DT = 64 * 16;  // documents per wave tile (16 per lane)
   const int64_t ecap = (int64_t)info.max_qlen + 1;
   const int64_t pcap = std::max<int64_t>(info.max_qlen, 1);
@@ -481,8 +482,11 @@ int search_plain_impl(bm25_index* idx, const int32_t* q_ids, const int64_t* q_of
   BM25_RESERVE(sc.members, (size_t)std::max<int64_t>(info.positions, 1) * 4);
   BM25_RESERVE(sc.dense_ent, (size_t)std::max<int64_t>(info.positions, 1) * sizeof(DenseEntry));
   BM25_RESERVE(sc.dense_n, (size_t)n * 4);
-  // candidate lists of up to kPlainMergeBatch queries, merged by one launch per batch
-  const int32_t mb = std::min<int32_t>(n, kPlainMergeBatch);
+  // candidate lists of up to kPlainMergeBatch queries (and at most kPlainCandBytes), merged by
+  // one launch per batch
+  const int64_t cand_per_query = G * KP * 8;
+  const int32_t mb = (int32_t)std::max<int64_t>(
+      1, std::min<int64_t>({(int64_t)n, (int64_t)kPlainMergeBatch, kPlainCandBytes / cand_per_query}));
   BM25_RESERVE(sc.cand, (size_t)mb * G * KP * 8);
   Staged dev;
   rc = upload_plan(sc, s, n, n, q_off, k, k_max, tile_q0, tile_e0, dev);

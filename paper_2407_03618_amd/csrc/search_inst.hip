@@ -81,15 +81,26 @@ static hipError_t sweep_one(dim3 g, size_t sh, hipStream_t s, const SweepArgs& a
   return hipGetLastError();
 }
 
+template <int W>
+static hipError_t sweep_w(int KPL, dim3 g, size_t sh, hipStream_t s, const SweepArgs& a) {
+  switch (KPL) {
+    case 1: return sweep_one<W, 1>(g, sh, s, a);
+    case 2: return sweep_one<W, 2>(g, sh, s, a);
+    case 4: return sweep_one<W, 4>(g, sh, s, a);
+    case 8: return sweep_one<W, 8>(g, sh, s, a);
+    case 16: return sweep_one<W, 16>(g, sh, s, a);
+    default: return hipErrorInvalidValue;
+  }
+}
+
+// Sweeps with 1, 2, 4 or 8 waves per workgroup.
 hipError_t BM25_CAT(launch_sweep_, BM25_ST_SUFFIX)(int W, int KPL, dim3 g, size_t sh,
                                                  hipStream_t s, const SweepArgs& a) {
-  if (W != 8) return hipErrorInvalidValue;
-  switch (KPL) {
-    case 1: return sweep_one<8, 1>(g, sh, s, a);
-    case 2: return sweep_one<8, 2>(g, sh, s, a);
-    case 4: return sweep_one<8, 4>(g, sh, s, a);
-    case 8: return sweep_one<8, 8>(g, sh, s, a);
-    case 16: return sweep_one<8, 16>(g, sh, s, a);
+  switch (W) {
+    case 1: return sweep_w<1>(KPL, g, sh, s, a);
+    case 2: return sweep_w<2>(KPL, g, sh, s, a);
+    case 4: return sweep_w<4>(KPL, g, sh, s, a);
+    case 8: return sweep_w<8>(KPL, g, sh, s, a);
     default: return hipErrorInvalidValue;
   }
 }
