@@ -114,6 +114,31 @@ def cpu_baseline_leg(corpus, queries, sample_idx, cfg, gpu_rows, threads):
                 affinity=len(os.sched_getaffinity(0))), worst
 
 
+def plain_1m_leg(nq: int) -> dict:
+    """The per-query form on its configured workload: 1M documents (V = 1M, Zipf 1.07, mean length
+    80), fp32 scores, top-100, one query per launch."""
+    import torch
+    from paper_2407_03618_amd import Index
+    from workloads import CONFIGS, make_corpus, make_queries
+    cfg = CONFIGS[1]
+    c = make_corpus(1)
+    q = make_queries(1, n_queries=nq, vocab=c.vocab)
+    dev = torch.device("cuda:0")
+    idx = Index(torch.from_numpy(c.tokens).to(dev), torch.from_numpy(c.doc_offsets).to(dev),
+                c.vocab, cfg["k1"], cfg["b"], cfg["delta"], cfg["variant"], "f32")
+    qd = torch.from_numpy(q.q_ids).to(dev)
+    out = idx._outputs(nq, 100)
+    idx.search_plain(qd, q.q_offsets, 100, 100, out=out)  # warm-up
+    torch.cuda.synchronize()
+    t0 = time.perf_counter()
+    idx.search_plain(qd, q.q_offsets, 100, 100, out=out)
+    torch.cuda.synchronize()
+    el = time.perf_counter() - t0
+    res = dict(qps=nq / el, ms_per_query=el / nq * 1e3, n_docs=c.n_docs, nnz=idx.nnz, queries=nq)
+    idx.free()
+    return res
+
+
 def _cpu_model():
     try:
         for line in open("/proc/cpuinfo"):
@@ -302,6 +327,8 @@ def main():
         torch.cuda.synchronize()
         extra["batched_fp32"] = dict(qps=reps * B / (time.perf_counter() - t0))
         log("[batched f32]", extra["batched_fp32"])
+        extra["plain_1M_fp32"] = plain_1m_leg(nq)
+        log("[plain 1M f32]", extra["plain_1M_fp32"])
 
     cpu = None
     if not args.no_cpu:
