@@ -22,6 +22,8 @@
 
 #include <cstdint>
 
+#include <type_traits>
+
 #include "device.hpp"
 
 namespace bm25dev {
@@ -794,9 +796,90 @@ __device__ __forceinline__ void take_lds(float* p, float* v) {
 // documents starting at tile document `first`. Loads run U = max(2, 16 / R) entries at a time
 // (16 values per lane) and the next group's loads are issued before the current group's
 // additions.
+// acc += a * (half in the low / high 16 bits of h2), one FMA rounding: v_fma_mix_f32 widens the
+// FP16 operand inside the multiply-add, so no separate conversion is issued.
+__device__ __forceinline__ void fma_mix_lo(float& acc, float a, uint32_t h2) {
+  asm("v_fma_mix_f32 %0, %1, %2, %0 op_sel_hi:[0,1,0]" : "+v"(acc) : "v"(a), "v"(h2));
+}
+__device__ __forceinline__ void fma_mix_hi(float& acc, float a, uint32_t h2) {
+  asm("v_fma_mix_f32 %0, %1, %2, %0 op_sel:[0,1,0] op_sel_hi:[0,1,0]"
+      : "+v"(acc)
+      : "v"(a), "v"(h2));
+}
+
+// accumulate_dense for FP16 rows: the stored halves stay packed in registers (R/2 words per
+// entry) and enter the FMAs directly.
+template <int QT, int R>
+__device__ __forceinline__ void accumulate_dense_f16(const IndexView& ix, const DenseEntry* de,
+                                                     int n, int64_t first,
+                                                     float (&acc)[QT][R]) {
+  static_assert(R % 2 == 0, "FP16 rows are read in pairs");
+  constexpr int U = (16 / R) > 2 ? (16 / R) : 2;
+  constexpr int NW = R / 2;
+  const __half* dense = reinterpret_cast<const __half*>(ix.dense) + first;
+  uint32_t w[2][U][NW];
+  uint32_t mk[2][U];
+  float mu[2][U];
+  auto load_group = [&](int e0, uint32_t (&dst)[U][NW], uint32_t (&m)[U], float (&f)[U]) {
+#pragma unroll
+    for (int u = 0; u < U; ++u) {
+      const int e = (e0 + u < n) ? e0 + u : n - 1;  // clamped: always a valid row
+      const DenseEntry d = de[e];
+      const uint32_t* q = reinterpret_cast<const uint32_t*>(dense + (int64_t)d.row * ix.n_pad);
+      if constexpr (NW % 4 == 0) {
+#pragma unroll
+        for (int i = 0; i < NW / 4; ++i) {
+          const uint4 x = reinterpret_cast<const uint4*>(q)[i];
+          dst[u][4 * i] = x.x;
+          dst[u][4 * i + 1] = x.y;
+          dst[u][4 * i + 2] = x.z;
+          dst[u][4 * i + 3] = x.w;
+        }
+      } else if constexpr (NW == 2) {
+        const uint2 x = reinterpret_cast<const uint2*>(q)[0];
+        dst[u][0] = x.x;
+        dst[u][1] = x.y;
+      } else {
+        dst[u][0] = q[0];
+      }
+      m[u] = (e0 + u < n) ? d.qmask : 0u;
+      f[u] = d.mult;
+    }
+  };
+  if (n <= 0) return;
+  load_group(0, w[0], mk[0], mu[0]);
+  for (int e0 = 0; e0 < n; e0 += 2 * U) {
+#pragma unroll
+    for (int h = 0; h < 2; ++h) {
+      const int eg = e0 + h * U;
+      if (eg >= n) break;
+      if (eg + U < n) load_group(eg + U, w[h ^ 1], mk[h ^ 1], mu[h ^ 1]);
+#pragma unroll
+      for (int u = 0; u < U; ++u) {
+        const uint32_t mask = mk[h][u];
+        const float mult = mu[h][u];
+#pragma unroll
+        for (int q = 0; q < QT; ++q) {
+          if ((mask >> q) & 1u) {
+#pragma unroll
+            for (int i = 0; i < NW; ++i) {
+              fma_mix_lo(acc[q][2 * i], mult, w[h][u][i]);
+              fma_mix_hi(acc[q][2 * i + 1], mult, w[h][u][i]);
+            }
+          }
+        }
+      }
+    }
+  }
+}
+
 template <typename ST, int QT, int R>
 __device__ __forceinline__ void accumulate_dense(const IndexView& ix, const DenseEntry* de, int n,
                                                  int64_t first, float (&acc)[QT][R]) {
+  if constexpr (std::is_same<ST, F16>::value) {
+    accumulate_dense_f16<QT, R>(ix, de, n, first, acc);
+    return;
+  }
   constexpr int U = (16 / R) > 2 ? (16 / R) : 2;
   const typename ST::T* dense = reinterpret_cast<const typename ST::T*>(ix.dense) + first;
   // values and (query mask, multiplier) of two groups of U entries: one in use, one loading
