@@ -555,7 +555,7 @@ __device__ __forceinline__ int32_t find_cursor(const IndexView& ix, int64_t row_
 
 // ------------------------------------------------------------------------------------------
 // Sweep state of the entries (query tokens) a wave walks through, structure of arrays in LDS:
-// static fields (row start, row length, skip-table row, member range) and the dynamic cursor
+// static fields (row start, row length, skip-table row, members) and the dynamic cursor
 // (offset of the next unconsumed entry of the row) plus, for rows without a skip table, the
 // document id at the cursor (INT32_MAX past the end), so that a tile without postings of that
 // row costs no memory access.
@@ -563,12 +563,37 @@ struct EntryState {
   int64_t* row_lo;
   int32_t* len;
   int32_t* lid;
-  int32_t* mem;  // member offset (relative to the LDS member copy) | member count << 16
+  int32_t* mem;  // see kInlineMember
   int32_t* cur;
   int32_t* nd;
 };
 
 constexpr int kEntryStaticBytes = 8 + 4 + 4 + 4;
+
+// Member field of an entry. Most entries have one member; its word (q_local | multiplicity
+// << 16) is then kept inline with this flag set. Otherwise the field is the member offset in the
+// LDS member copy | member count << 16.
+constexpr uint32_t kInlineMember = 0x80000000u;
+
+struct Members {
+  uint32_t first;  // the first member word
+  int count;
+  uint32_t off;    // offset of the members in the LDS copy (count > 1)
+};
+
+__device__ __forceinline__ Members decode_members(uint32_t w, const int32_t* mem_lds) {
+  Members m;
+  if (w & kInlineMember) {
+    m.first = w & ~kInlineMember;
+    m.count = 1;
+    m.off = 0;
+  } else {
+    m.count = (int)(w >> 16);
+    m.off = w & 0xFFFFu;
+    m.first = (m.count > 0) ? (uint32_t)mem_lds[m.off] : 0u;
+  }
+  return m;
+}
 constexpr int kEntryDynBytes = 4 + 4;
 
 __device__ __forceinline__ EntryState carve_state(uint8_t* base, int cap, int dyn_copies,
@@ -585,15 +610,18 @@ __device__ __forceinline__ EntryState carve_state(uint8_t* base, int cap, int dy
   return st;
 }
 
-// Loads static fields of entries [e_lo, e_hi) (lane-parallel) from the planner table.
-__device__ __forceinline__ void load_static(const Entry* ents, int e_lo, int e_hi,
-                                            int64_t mem_base, const EntryState& st) {
+// Loads static fields of entries [e_lo, e_hi) (lane-parallel) from the planner table and the
+// member list.
+__device__ __forceinline__ void load_static(const Entry* ents, const int32_t* members, int e_lo,
+                                            int e_hi, int64_t mem_base, const EntryState& st) {
   for (int j = e_lo + lane(); j < e_hi; j += 64) {
     const Entry en = ents[j];
     st.row_lo[j] = en.row_lo;
     st.len[j] = (int32_t)(en.row_hi - en.row_lo);
     st.lid[j] = en.long_id;
-    st.mem[j] = (int32_t)((en.mem_off - mem_base) | ((int64_t)en.mem_cnt << 16));
+    st.mem[j] = (en.mem_cnt == 1)
+                    ? (int32_t)((uint32_t)members[en.mem_off] | kInlineMember)
+                    : (int32_t)((en.mem_off - mem_base) | ((int64_t)en.mem_cnt << 16));
   }
 }
 
@@ -679,13 +707,17 @@ __device__ __forceinline__ void accumulate_tile(const IndexView& ix, const Entry
       }
 #pragma unroll
       for (int u = 0; u < U; ++u) {
-        const uint32_t w = (uint32_t)memw[u];
-        const int mcnt = (int)(w >> 16);
-        const int32_t mem = (l < mcnt) ? mem_lds[(w & 0xFFFFu) + l] : 0;
-        for (int m = 0; m < mcnt; ++m) {
-          const uint32_t mm = readlane((uint32_t)mem, m);
-          const float v = sv[u] * (float)(mm >> 16);
-          if (rel[u] >= 0) atomicAdd(acc + (int)(mm & 0xFFFFu) * DT + rel[u], v);
+        // a single member comes inline with the entry; more (rare) from the LDS member copy
+        const Members ms = decode_members((uint32_t)memw[u], mem_lds);
+        if (ms.count > 0 && rel[u] >= 0)
+          atomicAdd(acc + (int)(ms.first & 0xFFFFu) * DT + rel[u], sv[u] * (float)(ms.first >> 16));
+        if (ms.count > 1) {
+          const int32_t mem = (l < ms.count) ? mem_lds[ms.off + l] : 0;
+          for (int m = 1; m < ms.count; ++m) {
+            const uint32_t mm = readlane((uint32_t)mem, m);
+            const float v = sv[u] * (float)(mm >> 16);
+            if (rel[u] >= 0) atomicAdd(acc + (int)(mm & 0xFFFFu) * DT + rel[u], v);
+          }
         }
       }
     }
@@ -696,9 +728,8 @@ __device__ __forceinline__ void accumulate_tile(const IndexView& ix, const Entry
       const int src = __builtin_ctzll(pending);
       pending &= pending - 1;
       const int64_t row = (int64_t)readlane64((uint64_t)rlo, src);
-      const uint32_t w = readlane((uint32_t)mw, src);
-      const int mcnt = (int)(w >> 16);
-      const int32_t mem = (l < mcnt) ? mem_lds[(w & 0xFFFFu) + l] : 0;
+      const Members ms = decode_members(readlane((uint32_t)mw, src), mem_lds);
+      const int32_t mem = (ms.count > 1 && l < ms.count) ? mem_lds[ms.off + l] : 0;
       const int32_t L = (int32_t)readlane((uint32_t)len, src);
       int32_t c = (int32_t)readlane((uint32_t)cur, src);
       int32_t ndnew;
@@ -712,7 +743,9 @@ __device__ __forceinline__ void accumulate_tile(const IndexView& ix, const Entry
         const bool v = d < t1i;
         const int32_t r = d - t0i;
         const bool ok = v && r >= 0;
-        for (int m = 0; m < mcnt; ++m) {
+        if (ok && ms.count > 0)
+          atomicAdd(acc + (int)(ms.first & 0xFFFFu) * DT + r, s * (float)(ms.first >> 16));
+        for (int m = 1; m < ms.count; ++m) {
           const uint32_t mm = readlane((uint32_t)mem, m);
           if (ok) atomicAdd(acc + (int)(mm & 0xFFFFu) * DT + r, s * (float)(mm >> 16));
         }
@@ -1082,7 +1115,7 @@ __global__ __launch_bounds__(W * 64) void k_gather(GatherArgs a) {
   const int64_t d_hi = (d_lo + a.group_docs < ix.n_docs) ? d_lo + a.group_docs : ix.n_docs;
 
   for (int i = threadIdx.x; i < P; i += W * 64) mem_lds[i] = bv.members[p0 + i];
-  load_static(bv.entries + e_base, e_lo, e_hi, p0, st);
+  load_static(bv.entries + e_base, bv.members, e_lo, e_hi, p0, st);
   if (d_lo < d_hi) init_cursors(ix, e_lo, e_hi, d_lo, st);
   {
     float4* a4 = reinterpret_cast<float4*>(rows);
@@ -1201,7 +1234,7 @@ __global__ __launch_bounds__(W * 64) void k_sweep(SweepArgs a) {
   const int cap = bv.q_k[q];
 
   for (int i = threadIdx.x; i < P; i += W * 64) mem_lds[i] = bv.members[p0 + i];
-  if (w == 0) load_static(bv.entries + e_base, 0, E, p0, st);
+  if (w == 0) load_static(bv.entries + e_base, bv.members, 0, E, p0, st);
   __syncthreads();
   if (d_lo < d_hi) init_cursors(ix, 0, E, d_lo, st);
   for (int i = l; i < DT / 4; i += 64)
