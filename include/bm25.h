@@ -179,8 +179,10 @@ int bm25_search_plain(const bm25_index* index, const int32_t* q_ids, const int64
  *   sparse_only 1: read every token from the sparse rows, ignoring the dense copies of the most
  *               frequent tokens' rows (same results within rounding; for testing)
  * Built shapes: waves 8 with doc_tile 1024 (2 documents per lane) or 2048 (4 per lane), waves 4
- * with doc_tile 1024 (4 per lane); q_tile * list registers <= 32, where a query's list takes
- * ceil(k_max / 64) registers (rounded up to a power of two). */
+ * with doc_tile 1024 (4 per lane). q_tile is waves times 1, 2 or 4 queries per wave; with L list
+ * registers per query (k_max / 64 rounded up to a power of two): 1 query per wave for any L,
+ * 2 for L <= 4, 4 for L <= 2 with waves * documents per lane <= 16. Plans outside these are
+ * rejected; a fixed plan whose q_tile is too large for a batch's k_max is narrowed. */
 typedef struct {
   int32_t q_tile;
   int32_t waves;
