@@ -953,8 +953,8 @@ __device__ __forceinline__ void accumulate_dense(const IndexView& ix, const Dens
   }
 }
 
-// Filters one accumulator row of a tile against the wave's current k-th key, offers the
-// survivors to the list and clears the row. A plain FP32 comparison with the k-th score
+// Filters one accumulator row of a tile against the wave's current k-th key and offers the
+// survivors to the list. A plain FP32 comparison with the k-th score
 // rejects most values; only chunks with a candidate build 64-bit keys.
 template <int KPL>
 __device__ __forceinline__ void select_row(float* rowp, int DT, int64_t t0, int64_t t1,
@@ -964,7 +964,6 @@ __device__ __forceinline__ void select_row(float* rowp, int DT, int64_t t0, int6
   float thr_s = (thr == 0) ? -INFINITY : key_score(thr);
   for (int i = l; i < DT / 4; i += 64) {
     const float4 v4 = row[i];
-    row[i] = make_float4(0.f, 0.f, 0.f, 0.f);
     const bool p = (v4.x >= thr_s) || (v4.y >= thr_s) || (v4.z >= thr_s) || (v4.w >= thr_s);
     if (ballot(p)) {
       const int64_t db = t0 + 4 * i;
@@ -989,7 +988,6 @@ __device__ __forceinline__ void select_row(float* rowp, int DT, int64_t t0, int6
   float thr_s = S.thr_score();
   for (int i = l; i < DT / 4; i += 64) {
     const float4 v4 = row[i];
-    row[i] = make_float4(0.f, 0.f, 0.f, 0.f);
     const bool p = (v4.x >= thr_s) || (v4.y >= thr_s) || (v4.z >= thr_s) || (v4.w >= thr_s);
     if (ballot(p)) {
       const int64_t db = t0 + 4 * i;
@@ -1023,6 +1021,21 @@ __device__ __forceinline__ void fold_lds(float* p, float* v) {
     x.x += v[0];
     x.y += v[1];
     reinterpret_cast<float2*>(p)[0] = x;
+  }
+#pragma unroll
+  for (int r = 0; r < R; ++r) v[r] = 0.f;
+}
+
+// Stores R register values into an LDS row (the lane owns these documents) and clears them.
+template <int R>
+__device__ __forceinline__ void put_lds(float* p, float* v) {
+  if constexpr (R % 4 == 0) {
+#pragma unroll
+    for (int i = 0; i < R / 4; ++i)
+      reinterpret_cast<float4*>(p)[i] = make_float4(v[4 * i], v[4 * i + 1], v[4 * i + 2], v[4 * i + 3]);
+  } else {
+    static_assert(R == 2, "unsupported width");
+    reinterpret_cast<float2*>(p)[0] = make_float2(v[0], v[1]);
   }
 #pragma unroll
   for (int r = 0; r < R; ++r) v[r] = 0.f;
@@ -1117,10 +1130,6 @@ __global__ __launch_bounds__(W * 64) void k_gather(GatherArgs a) {
   for (int i = threadIdx.x; i < P; i += W * 64) mem_lds[i] = bv.members[p0 + i];
   load_static(bv.entries + e_base, bv.members, e_lo, e_hi, p0, st);
   if (d_lo < d_hi) init_cursors(ix, e_lo, e_hi, d_lo, st);
-  {
-    float4* a4 = reinterpret_cast<float4*>(rows);
-    for (int i = threadIdx.x; i < QT * DT / 4; i += W * 64) a4[i] = make_float4(0.f, 0.f, 0.f, 0.f);
-  }
   float acc[QT][R];
 #pragma unroll
   for (int q = 0; q < QT; ++q)
@@ -1149,15 +1158,15 @@ __global__ __launch_bounds__(W * 64) void k_gather(GatherArgs a) {
 
   for (int64_t t0 = d_lo; t0 < d_hi; t0 += DT) {
     const int64_t t1 = (t0 + DT < d_hi) ? t0 + DT : d_hi;
-    accumulate_tile<ST>(ix, st, e_lo, e_hi, mem_lds, rows, DT, t0, t1);
+    // dense rows first, stored (not added) over the previous tile's slots, then the sparse rows
+    // added on top: no slot is ever cleared
     accumulate_dense<ST, QT, R>(ix, dent, n_dense, t0 + first, acc);
-    __syncthreads();
-    if (n_dense > 0) {
 #pragma unroll
-      for (int q = 0; q < QT; ++q)
-        if (q < nq) fold_lds<R>(rows + q * DT + first, acc[q]);
-      __syncthreads();
-    }
+    for (int q = 0; q < QT; ++q)
+      if (q < nq) put_lds<R>(rows + q * DT + first, acc[q]);
+    __syncthreads();
+    accumulate_tile<ST>(ix, st, e_lo, e_hi, mem_lds, rows, DT, t0, t1);
+    __syncthreads();
 #pragma unroll
     for (int j = 0; j < QPW; ++j) {
       const int ql = w * QPW + j;
