@@ -1159,8 +1159,10 @@ __global__ __launch_bounds__(W * 64) void k_gather(GatherArgs a) {
   for (int64_t t0 = d_lo; t0 < d_hi; t0 += DT) {
     const int64_t t1 = (t0 + DT < d_hi) ? t0 + DT : d_hi;
     // dense rows first, stored (not added) over the previous tile's slots, then the sparse rows
-    // added on top: no slot is ever cleared
+    // added on top: no slot is ever cleared. The dense rows go to registers while slower waves
+    // still select from the previous tile; the barrier comes before the stores.
     accumulate_dense<ST, QT, R>(ix, dent, n_dense, t0 + first, acc);
+    __syncthreads();
 #pragma unroll
     for (int q = 0; q < QT; ++q)
       if (q < nq) put_lds<R>(rows + q * DT + first, acc[q]);
@@ -1177,7 +1179,6 @@ __global__ __launch_bounds__(W * 64) void k_gather(GatherArgs a) {
           select_row<KPL>(rows + ql * DT, DT, t0, t1, L[j], cap[j], thr[j]);
       }
     }
-    __syncthreads();
   }
 #pragma unroll
   for (int j = 0; j < QPW; ++j) {
