@@ -29,10 +29,6 @@ __device__ __forceinline__ uint64_t readlane64(uint64_t v, int l) {
   return ((uint64_t)hi << 32) | lo;
 }
 
-__device__ __forceinline__ int64_t readlane_i64(int64_t v, int l) {
-  return (int64_t)readlane64((uint64_t)v, l);
-}
-
 // Value of lane `src` (0..63) for every lane, through the LDS crossbar (no memory traffic).
 __device__ __forceinline__ uint32_t bperm(uint32_t v, int src) {
   return (uint32_t)__builtin_amdgcn_ds_bpermute(src << 2, (int)v);

@@ -1002,30 +1002,6 @@ __device__ __forceinline__ void select_row(float* rowp, int DT, int64_t t0, int6
   }
 }
 
-// Adds R register values into an LDS row (the lane owns these documents) and clears them.
-template <int R>
-__device__ __forceinline__ void fold_lds(float* p, float* v) {
-  if constexpr (R % 4 == 0) {
-#pragma unroll
-    for (int i = 0; i < R / 4; ++i) {
-      float4 x = reinterpret_cast<float4*>(p)[i];
-      x.x += v[4 * i];
-      x.y += v[4 * i + 1];
-      x.z += v[4 * i + 2];
-      x.w += v[4 * i + 3];
-      reinterpret_cast<float4*>(p)[i] = x;
-    }
-  } else {
-    static_assert(R == 2, "unsupported width");
-    float2 x = reinterpret_cast<float2*>(p)[0];
-    x.x += v[0];
-    x.y += v[1];
-    reinterpret_cast<float2*>(p)[0] = x;
-  }
-#pragma unroll
-  for (int r = 0; r < R; ++r) v[r] = 0.f;
-}
-
 // Stores R register values into an LDS row (the lane owns these documents) and clears them.
 template <int R>
 __device__ __forceinline__ void put_lds(float* p, float* v) {
@@ -1062,11 +1038,12 @@ __device__ __forceinline__ void select_regs(const float* v, int64_t first, int64
 // ------------------------------------------------------------------------------------------
 // Batched gather + top-k. Workgroup = (query tile of up to QT queries, doc group), W waves.
 // A tile spans DT = W * 64 * R documents; lane l of wave w owns documents w*64*R + l*R .. +R-1
-// of the tile for every query of the tile, with FP32 accumulators in registers. Dense-row
-// tokens are added straight into the registers; the other tokens' postings are added into an
-// LDS accumulator row per query. Once per tile the lanes fold their registers into those rows
-// (each lane owns its documents: no atomics), and the wave owning a query filters its row
-// against the query's k-th key (QPW = QT / W queries per wave, one list each).
+// of the tile for every query of the tile, with FP32 accumulators in registers. Once per tile:
+// the dense-row tokens are added into the registers, which the lanes then store into an LDS
+// accumulator row per query (each lane owns its documents: plain stores over the previous
+// tile's values); the other tokens' postings are added on top with LDS atomics; and the wave
+// owning a query filters its row against the query's k-th key (QPW = QT / W queries per wave,
+// one list each).
 //
 // LDS: accumulator rows [QT][DT] | entry static fields [ecap] | cursors [ecap] |
 //      member copy [pcap].
