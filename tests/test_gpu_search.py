@@ -224,3 +224,19 @@ def test_query_order_grouped_matches_given():
     check_batch(ref2, q_ids2, q_off2, qb2.k, ids, sc, cnt, RTOL["f16"], "long query",
                 sample=range(0, 200, 7))
     torch.cuda.synchronize()
+
+
+def test_empty_document_groups():
+    """More document groups than the corpus fills: groups past the last document write empty
+    lists that the merge skips (10 document tiles over 8 groups of 2 tiles)."""
+    import torch
+    c = make_corpus(2, n_docs=10_000)
+    q = make_queries(2, n_queries=40, vocab=c.vocab, k=30)
+    ref = eager.build_index(c.tokens, c.doc_offsets, c.vocab, token_subset=np.unique(q.q_ids))
+    idx = _index(c, dtype="f16")
+    for plan in (dict(q_tile=8, waves=4, doc_tile=1024, doc_groups=8),
+                 dict(q_tile=16, waves=8, doc_tile=2048, doc_groups=7)):
+        idx.set_plan(plan)
+        ids, sc, cnt = _run(idx, q, 30, "batch")
+        check_batch(ref, q.q_ids, q.q_offsets, q.k, ids, sc, cnt, RTOL["f16"], str(plan))
+    torch.cuda.synchronize()
