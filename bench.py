@@ -139,6 +139,45 @@ def plain_1m_leg(nq: int) -> dict:
     return res
 
 
+def long_docs_leg(n_batches: int = 4, batch: int = 512) -> dict:
+    """The shifted-variant workload at full size: 5M long documents (mean 300 ids, V = 3M,
+    Zipf 1.0), BM25+ (k1 = 1.2, b = 0.75, delta = 1), bf16 scores, 30-200-id queries, top-1000,
+    batched form."""
+    import torch
+    from paper_2407_03618_amd import Index
+    from workloads import CONFIGS, make_corpus, make_queries
+    cfg = CONFIGS[3]
+    c = make_corpus(3)
+    q = make_queries(3, n_queries=batch * (n_batches + 1), vocab=c.vocab)
+    dev = torch.device("cuda:0")
+    tok = torch.from_numpy(c.tokens).to(dev)
+    off = torch.from_numpy(c.doc_offsets).to(dev)
+    torch.cuda.synchronize()
+    t0 = time.perf_counter()
+    idx = Index(tok, off, c.vocab, cfg["k1"], cfg["b"], cfg["delta"], cfg["variant"], "bf16")
+    torch.cuda.synchronize()
+    build_ms = (time.perf_counter() - t0) * 1e3
+    del tok, off
+    torch.cuda.empty_cache()
+    qd = torch.from_numpy(q.q_ids).to(dev)
+    k = int(cfg["k"])
+    out = idx._outputs(batch, k)
+    idx.search_batch(qd, q.q_offsets[:batch + 1], k, k, out=out)  # warm-up
+    torch.cuda.synchronize()
+    t0 = time.perf_counter()
+    for b in range(1, n_batches + 1):
+        o = q.q_offsets[b * batch:(b + 1) * batch + 1]
+        base = int(o[0])
+        idx.search_batch(qd[base:], o - base, k, k, out=out)
+    torch.cuda.synchronize()
+    el = time.perf_counter() - t0
+    res = dict(qps=n_batches * batch / el, ms_per_batch=el / n_batches * 1e3, batch=batch, k=k,
+               n_docs=c.n_docs, nnz=idx.nnz, build_ms=build_ms,
+               build_nnz_per_s=idx.nnz / (build_ms / 1e3), variant=cfg["variant"], dtype="bf16")
+    idx.free()
+    return res
+
+
 def _cpu_model():
     try:
         for line in open("/proc/cpuinfo"):
@@ -189,6 +228,7 @@ def main():
     ap.add_argument("--no-cpu", action="store_true")
     ap.add_argument("--no-plain", action="store_true")
     ap.add_argument("--no-serve", action="store_true")
+    ap.add_argument("--no-long", action="store_true", help="skip the 5M long-document leg")
     ap.add_argument("--autotune", action="store_true")
     args = ap.parse_args()
     if args.gpus != 1 or int(os.environ.get("WORLD_SIZE", "1")) != 1:
@@ -340,6 +380,12 @@ def main():
         extra["parity"] = dict(queries_checked=ns, max_rel_err=worst, rtol=2e-3,
                                rule="score within rtol of sum |S|; ids match up to ties")
         log("[cpu]", cpu)
+
+    if not args.no_long:
+        idx32.free()  # the fp32 index is no longer needed: make room for the 5M-document one
+        torch.cuda.empty_cache()
+        extra["long_docs_bm25plus_bf16_top1000"] = long_docs_leg()
+        log("[long docs]", extra["long_docs_bm25plus_bf16_top1000"])
 
     if not args.no_serve:
         extra["serving"] = serving_leg(idx, corpus, CONFIGS[4]["rates"], args.serve_seconds,
