@@ -173,9 +173,10 @@ struct PlanSmem {
 
 #ifdef BM25_SEARCH_MAIN
 // Query grouping: one workgroup per window of up to kPlanSort consecutive queries. A query's
-// signature has one bit per dense row it holds (the most frequent row in the highest bit); the
-// window is sorted by signature, descending, then by position, so that queries sharing frequent
-// rows fall into the same query tile and that tile reads each shared dense row once. Writes the
+// signature has one bit per dense row it holds (the least frequent row in the highest bit); the
+// window is sorted by signature, descending, then by position, so that queries holding the same
+// dense rows, the rarer ones deciding first, fall into the same query tile, and that tile reads
+// each shared dense row once (the most frequent rows are in most tiles anyway). Writes the
 // grouped batch (ids, offsets, k) and perm[grouped index] = caller's index.
 struct ReorderArgs {
   const int32_t* q_ids;
@@ -227,7 +228,7 @@ __global__ __launch_bounds__(kPlanThreads) void k_reorder(ReorderArgs a) {
       if (qoff[mid] <= (uint32_t)p) lo = mid; else hi = mid - 1;
     }
     atomicOr(reinterpret_cast<unsigned long long*>(key + lo),
-             (unsigned long long)(1ull << (kSigBits - 1 - r)));
+             (unsigned long long)(1ull << r));
   }
   __syncthreads();
   // sort by signature descending, then position; padding sorts last (a real key has a zero
