@@ -178,6 +178,38 @@ def long_docs_leg(n_batches: int = 4, batch: int = 512) -> dict:
     return res
 
 
+def graph_leg(idx, q_dev, queries, k, first, full_batch, reps=40, small=64) -> dict:
+    """Eager launches against one HIP graph launch per batch (graph mode), on 64-query
+    micro-batches (where launch gaps weigh most) and on full batches."""
+    import torch
+    res = {}
+    for name, n, r in (("micro_batch_64", small, reps), ("batch_full", full_batch, 4)):
+        out = idx._outputs(n, k)
+
+        def run(i):
+            lo = first + i * n
+            off = queries.q_offsets[lo:lo + n + 1]
+            base = int(off[0])
+            idx.search_batch(q_dev[base:], off - base, k, k, out=out)
+
+        row = {}
+        for mode in (False, True):
+            idx.set_graphs(mode)
+            run(0)
+            run(1)
+            torch.cuda.synchronize()
+            t0 = time.perf_counter()
+            for i in range(r):
+                run(i % 2)
+            torch.cuda.synchronize()
+            dt = (time.perf_counter() - t0) / r
+            row["graph" if mode else "eager"] = dict(ms_per_batch=dt * 1e3, qps=n / dt)
+        idx.set_graphs(False)
+        res[name] = row
+    res["graph_stats"] = idx.graph_stats()
+    return res
+
+
 def _cpu_model():
     try:
         for line in open("/proc/cpuinfo"):
@@ -229,6 +261,7 @@ def main():
     ap.add_argument("--no-plain", action="store_true")
     ap.add_argument("--no-serve", action="store_true")
     ap.add_argument("--no-long", action="store_true", help="skip the 5M long-document leg")
+    ap.add_argument("--no-graph", action="store_true", help="skip the HIP graph leg")
     ap.add_argument("--autotune", action="store_true")
     args = ap.parse_args()
     if args.gpus != 1 or int(os.environ.get("WORLD_SIZE", "1")) != 1:
@@ -329,6 +362,9 @@ def main():
     ids_h, sc_h, cnt_h = (t.cpu().numpy() for t in out)
 
     extra = {}
+    if not args.no_graph:
+        extra["graph_mode"] = graph_leg(idx, q_dev, queries, k, 0, B)
+        log("[graph]", extra["graph_mode"])
     # plain per-query FP32 form on the same index recipe
     if not args.no_plain:
         nq = args.plain_queries

@@ -151,8 +151,10 @@ void bm25_index_free(bm25_index* index);
  * n_queries < 0, k out of range, malformed q_offsets or a query longer than the limit.
  *
  * bm25_search_batch runs the batched form: queries are grouped into tiles that share posting
- * reads, accumulated in LDS-resident FP32 tiles and reduced to top-k inside one persistent
- * kernel per batch (launch shape from the autotuner or bm25_search_set_plan).
+ * reads, accumulated in LDS-resident FP32 tiles and reduced to per-(query, document range)
+ * top-k lists inside one gather kernel per batch (launch shape from the autotuner or
+ * bm25_search_set_plan), then merged per query. With graph mode on (bm25_search_set_graphs) the
+ * batch's launches after the plan upload run as one HIP graph launch.
  * bm25_search_plain runs the per-query form: each query is one launch that sweeps all
  * documents for that query alone (about 2048 one-wave workgroups, each over a contiguous range
  * of whole 1024-document blocks); one small merge launch per up to 256 queries then ranks each
@@ -199,6 +201,22 @@ int bm25_search_set_plan(bm25_index* index, const bm25_tile_plan* plan);
 /* Reads the plan the batched form would use for a batch of the given shape. */
 int bm25_search_get_plan(const bm25_index* index, int32_t n_queries, int32_t max_query_len,
                          int32_t k_max, bm25_tile_plan* plan);
+
+/* Graph mode for the batched form (Section 2, "Multi-threading": many queries per submission,
+ * carried to one device submission per batch). enable != 0: every later bm25_search_batch on
+ * this index, and every micro-batch of a server over it, records its launches (grouping,
+ * planner, gather, merge; kernels only, no memset or copy nodes) into a HIP graph on a private
+ * capture stream and launches that graph on the caller's stream as one submission. The plan
+ * upload stays an ordinary copy on the caller's stream ahead of the graph. The executable graph
+ * is kept per scratch area and updated in place when the next batch has the same launch
+ * topology (arguments and grid sizes may change), else instantiated anew. Results are those of
+ * the eager path. With kernel timing enabled, the timing events bracket the whole graph.
+ * enable == 0 (the default) returns to eager launches. BM25_E_INVAL for a NULL index. */
+int bm25_search_set_graphs(bm25_index* index, int32_t enable);
+
+/* Graph-mode counters of bm25_search_batch on this index: graph instantiations (*builds) and
+ * in-place updates (*updates) since the index was built. BM25_E_INVAL for NULL arguments. */
+int bm25_search_graph_stats(const bm25_index* index, int64_t* builds, int64_t* updates);
 
 /* Autotuner: times candidate launch shapes of the batched form on the given batch (same
  * arguments as bm25_search_batch; results are written to the outputs by every candidate), keeps

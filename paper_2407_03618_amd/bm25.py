@@ -30,7 +30,8 @@ OK, E_INVAL, E_RANGE, E_NOMEM, E_BUSY, E_HIP, E_STATE, E_TIMEOUT = 0, -1, -2, -3
 EXPORTED = (
     "bm25_index_build", "bm25_index_info", "bm25_index_export", "bm25_index_device_bytes",
     "bm25_index_free", "bm25_search_batch", "bm25_search_plain", "bm25_search_set_plan",
-    "bm25_search_get_plan", "bm25_autotune", "bm25_kernel_timing", "bm25_kernel_time_read",
+    "bm25_search_get_plan", "bm25_search_set_graphs", "bm25_search_graph_stats",
+    "bm25_autotune", "bm25_kernel_timing", "bm25_kernel_time_read",
     "bm25_serve_create", "bm25_serve_submit", "bm25_serve_poll", "bm25_serve_stats",
     "bm25_serve_replay", "bm25_serve_destroy", "bm25_copy_bytes", "bm25_last_error",
 )
@@ -87,6 +88,8 @@ def load_library() -> ctypes.CDLL:
         fn.argtypes = [vp, vp, vp, i32, vp, i32, vp, vp, vp, vp]
     L.bm25_search_set_plan.argtypes = [vp, P(TilePlan)]
     L.bm25_search_get_plan.argtypes = [vp, i32, i32, i32, P(TilePlan)]
+    L.bm25_search_set_graphs.argtypes = [vp, i32]
+    L.bm25_search_graph_stats.argtypes = [vp, P(i64), P(i64)]
     L.bm25_autotune.argtypes = [vp, vp, vp, i32, vp, i32, vp, vp, vp, vp, P(TilePlan)]
     L.bm25_kernel_timing.argtypes = [vp, i32]
     L.bm25_kernel_time_read.argtypes = [vp, P(dbl), P(i64)]
@@ -284,6 +287,17 @@ class Index:
             None if k_arr is None else k_arr.ctypes.data, int(k_max), _ptr(ids), _ptr(scores),
             _ptr(count), _stream_ptr(stream), ctypes.byref(best)))
         return best.as_dict()
+
+    def set_graphs(self, enable: bool) -> None:
+        """Graph mode: each later batched search (and server micro-batch) is one HIP graph
+        launch."""
+        _check(load_library().bm25_search_set_graphs(self._h, 1 if enable else 0))
+
+    def graph_stats(self) -> dict:
+        b = ctypes.c_int64()
+        u = ctypes.c_int64()
+        _check(load_library().bm25_search_graph_stats(self._h, ctypes.byref(b), ctypes.byref(u)))
+        return {"builds": b.value, "updates": u.value}
 
     def kernel_timing(self, enable: bool) -> None:
         _check(load_library().bm25_kernel_timing(self._h, 1 if enable else 0))

@@ -785,7 +785,6 @@ extern "C" void bm25_index_free(bm25_index* index) {
     (void)hipEventDestroy(ev.first);
     (void)hipEventDestroy(ev.second);
   }
-  for (auto* sc : {&index->batch_scratch, &index->plain_scratch})
-    if (sc->host_free) (void)hipEventDestroy(sc->host_free);
+  for (auto* sc : {&index->batch_scratch, &index->plain_scratch}) sc->release_handles();
   delete index;
 }

@@ -3,6 +3,7 @@
 
 #include <hip/hip_runtime.h>
 
+#include <array>
 #include <cstdint>
 #include <cstdio>
 #include <map>
@@ -129,6 +130,23 @@ struct SearchScratch {
   DevBuf k2;
   PinnedBuf host;   // staging for the host-side plan
   hipEvent_t host_free = nullptr;  // the staging buffer may be rewritten once this has fired
+  // graph mode: launches are recorded on cap_stream (capture only, nothing runs there) and the
+  // instantiated graph is kept for the next batch, updated in place while its topology holds
+  hipStream_t cap_stream = nullptr;
+  hipGraphExec_t graph_exec = nullptr;
+  std::array<int64_t, 10> graph_cfg{};  // launch configuration the kept graph was captured with
+  int64_t graph_builds = 0;    // instantiations
+  int64_t graph_updates = 0;   // in-place updates
+
+  // Destroys the events, streams and graphs (device buffers free themselves).
+  void release_handles() {
+    if (graph_exec) (void)hipGraphExecDestroy(graph_exec);
+    if (cap_stream) (void)hipStreamDestroy(cap_stream);
+    if (host_free) (void)hipEventDestroy(host_free);
+    graph_exec = nullptr;
+    cap_stream = nullptr;
+    host_free = nullptr;
+  }
 };
 
 struct TileShape {
@@ -177,6 +195,8 @@ struct bm25_index {
   bool plan_fixed = false;
   bm25::TileShape fixed_plan;
   std::map<uint64_t, bm25::TileShape> tuned;  // shape class -> tuned plan
+
+  bool use_graphs = false;  // batched searches run as one HIP graph launch each
 
   bool timing = false;
   std::vector<std::pair<hipEvent_t, hipEvent_t>> timing_events;

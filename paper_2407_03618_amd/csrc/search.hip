@@ -267,6 +267,57 @@ static int timed_end(bm25_index* idx, hipStream_t s, hipEvent_t b) {
   return BM25_OK;
 }
 
+// Records the launches that `enqueue` issues into a HIP graph on the scratch's capture stream
+// (capture only: nothing runs there) and launches the graph on `s`. The executable graph is kept;
+// the next batch with the same launch configuration `cfg` (same kernels, grid and LDS sizes: only
+// pointers and scalar arguments differ) updates it in place, any other is instantiated anew. The
+// captured sequence holds kernel launches only, no memset or copy nodes.
+template <typename F>
+static int launch_as_graph(SearchScratch& sc, hipStream_t s, const std::array<int64_t, 10>& cfg,
+                           F& enqueue) {
+  if (!sc.cap_stream) BM25_HIP(hipStreamCreateWithFlags(&sc.cap_stream, hipStreamNonBlocking));
+  BM25_HIP(hipStreamBeginCapture(sc.cap_stream, hipStreamCaptureModeThreadLocal));
+  const int rc = enqueue(sc.cap_stream);
+  hipGraph_t g = nullptr;
+  const hipError_t ec = hipStreamEndCapture(sc.cap_stream, &g);
+  if (rc != BM25_OK || ec != hipSuccess) {
+    if (g) (void)hipGraphDestroy(g);
+    if (rc != BM25_OK) return rc;
+    return set_error(BM25_E_HIP, "graph capture failed: %s", hipGetErrorString(ec));
+  }
+  bool updated = false;
+  if (sc.graph_exec && sc.graph_cfg != cfg) {
+    (void)hipGraphExecDestroy(sc.graph_exec);
+    sc.graph_exec = nullptr;
+  }
+  if (sc.graph_exec) {
+    hipGraphNode_t bad = nullptr;
+    hipGraphExecUpdateResult res = hipGraphExecUpdateError;
+    if (hipGraphExecUpdate(sc.graph_exec, g, &bad, &res) == hipSuccess &&
+        res == hipGraphExecUpdateSuccess) {
+      updated = true;
+      ++sc.graph_updates;
+    } else {
+      (void)hipGetLastError();  // a refused update is not an error of this call
+      (void)hipGraphExecDestroy(sc.graph_exec);
+      sc.graph_exec = nullptr;
+    }
+  }
+  if (!updated) {
+    const hipError_t ei = hipGraphInstantiate(&sc.graph_exec, g, nullptr, nullptr, 0);
+    if (ei != hipSuccess) {
+      sc.graph_exec = nullptr;
+      (void)hipGraphDestroy(g);
+      return set_error(BM25_E_HIP, "graph instantiation failed: %s", hipGetErrorString(ei));
+    }
+    ++sc.graph_builds;
+    sc.graph_cfg = cfg;
+  }
+  (void)hipGraphDestroy(g);
+  BM25_HIP(hipGraphLaunch(sc.graph_exec, s));
+  return BM25_OK;
+}
+
 int search_batch_impl(bm25_index* idx, const int32_t* q_ids, const int64_t* q_off, int32_t n,
                       const int32_t* k, int32_t k_max, int32_t* out_ids, float* out_scores,
                       int32_t* out_count, hipStream_t s, SearchScratch& sc,
@@ -358,23 +409,9 @@ int search_batch_impl(bm25_index* idx, const int32_t* q_ids, const int64_t* q_of
   rc = upload_plan(sc, s, n, n_tiles, q_off, k, k_max, tile_q0, tile_e0, dev);
   if (rc != BM25_OK) return rc;
 
-  const int32_t* b_ids = q_ids;
-  const int64_t* b_off = dev.q_off;
-  const int32_t* b_k = dev.q_k;
   if (grouped) {
-    ReorderArgs ra;
-    ra.q_ids = q_ids;
-    ra.q_off = dev.q_off;
-    ra.q_k = dev.q_k;
-    ra.dense_id = ix.dense_id;
-    ra.dense_rank = ix.dense_rank;
-    ra.vocab = idx->vocab;
-    ra.n = n;
-    ra.ids2 = sc.ids2.as<int32_t>();
-    ra.off2 = sc.off2.as<int64_t>();
-    ra.k2 = sc.k2.as<int32_t>();
-    ra.perm = sc.perm.as<int32_t>();
-    // the kernel takes more than the default 64 KB of LDS (setting it twice is harmless)
+    // the kernel takes more than the default 64 KB of LDS (setting it twice is harmless); set
+    // before any capture begins
     static std::atomic<bool> reorder_lds{false};
     if (!reorder_lds.load(std::memory_order_acquire)) {
       BM25_HIP(hipFuncSetAttribute((const void*)k_reorder,
@@ -382,64 +419,99 @@ int search_batch_impl(bm25_index* idx, const int32_t* q_ids, const int64_t* q_of
                                    (int)kReorderLds));
       reorder_lds.store(true, std::memory_order_release);
     }
-    hipLaunchKernelGGL(k_reorder, dim3((unsigned)((n + kPlanSort - 1) / kPlanSort)),
-                       dim3(kPlanThreads), kReorderLds, s, ra);
-    BM25_HIP(hipGetLastError());
-    b_ids = ra.ids2;
-    b_off = ra.off2;
-    b_k = ra.k2;
   }
-  BatchView bv;
-  bv.q_ids = b_ids;
-  bv.q_off = b_off;
-  bv.q_k = b_k;
-  bv.q_stat = sc.qstat.as<int32_t>();
-  bv.tile_q0 = dev.tile_q0;
-  bv.tile_e0 = dev.tile_e0;
-  bv.wave_e0 = sc.wave_e0.as<int32_t>();
-  bv.entries = sc.entries.as<Entry>();
-  bv.members = sc.members.as<int32_t>();
-  bv.dense_ent = sc.dense_ent.as<DenseEntry>();
-  bv.dense_n = sc.dense_n.as<int32_t>();
-  bv.n_queries = n;
-  bv.n_tiles = n_tiles;
+  const bool graph = idx->use_graphs;
+  // Everything after the plan upload: grouping, planner, gather, merge. Enqueued on `q`, which
+  // is the caller's stream, or the capture stream in graph mode.
+  auto enqueue = [&](hipStream_t q) -> int {
+    const int32_t* b_ids = q_ids;
+    const int64_t* b_off = dev.q_off;
+    const int32_t* b_k = dev.q_k;
+    if (grouped) {
+      ReorderArgs ra;
+      ra.q_ids = q_ids;
+      ra.q_off = dev.q_off;
+      ra.q_k = dev.q_k;
+      ra.dense_id = ix.dense_id;
+      ra.dense_rank = ix.dense_rank;
+      ra.vocab = idx->vocab;
+      ra.n = n;
+      ra.ids2 = sc.ids2.as<int32_t>();
+      ra.off2 = sc.off2.as<int64_t>();
+      ra.k2 = sc.k2.as<int32_t>();
+      ra.perm = sc.perm.as<int32_t>();
+      hipLaunchKernelGGL(k_reorder, dim3((unsigned)((n + kPlanSort - 1) / kPlanSort)),
+                         dim3(kPlanThreads), kReorderLds, q, ra);
+      BM25_HIP(hipGetLastError());
+      b_ids = ra.ids2;
+      b_off = ra.off2;
+      b_k = ra.k2;
+    }
+    BatchView bv;
+    bv.q_ids = b_ids;
+    bv.q_off = b_off;
+    bv.q_k = b_k;
+    bv.q_stat = sc.qstat.as<int32_t>();
+    bv.tile_q0 = dev.tile_q0;
+    bv.tile_e0 = dev.tile_e0;
+    bv.wave_e0 = sc.wave_e0.as<int32_t>();
+    bv.entries = sc.entries.as<Entry>();
+    bv.members = sc.members.as<int32_t>();
+    bv.dense_ent = sc.dense_ent.as<DenseEntry>();
+    bv.dense_n = sc.dense_n.as<int32_t>();
+    bv.n_queries = n;
+    bv.n_tiles = n_tiles;
 
-  hipLaunchKernelGGL(k_plan, dim3(n_tiles), dim3(kPlanThreads), 0, s, ix, bv, W);
-  BM25_HIP(hipGetLastError());
+    hipLaunchKernelGGL(k_plan, dim3(n_tiles), dim3(kPlanThreads), 0, q, ix, bv, W);
+    BM25_HIP(hipGetLastError());
 
-  GatherArgs ga;
-  ga.ix = ix;
-  ga.bv = bv;
-  ga.cand = sc.cand.as<uint64_t>();
-  ga.group_docs = group_docs;
-  ga.n_groups = (int32_t)G;
-  ga.ecap = (int32_t)ecap;
-  ga.pcap = (int32_t)pcap;
-  hipEvent_t tb;
+    GatherArgs ga;
+    ga.ix = ix;
+    ga.bv = bv;
+    ga.cand = sc.cand.as<uint64_t>();
+    ga.group_docs = group_docs;
+    ga.n_groups = (int32_t)G;
+    ga.ecap = (int32_t)ecap;
+    ga.pcap = (int32_t)pcap;
+    hipEvent_t tb = nullptr;
+    int r = graph ? BM25_OK : timed_begin(idx, q, &tb);
+    if (r != BM25_OK) return r;
+    BM25_HIP(launch_gather(idx->params.store_dtype, W, QT, R, KPL,
+                           dim3((unsigned)((int64_t)n_tiles * G)), (size_t)lds, q, ga));
+    r = graph ? BM25_OK : timed_end(idx, q, tb);
+    if (r != BM25_OK) return r;
+
+    MergeArgs ma;
+    ma.cand = sc.cand.as<uint64_t>();
+    ma.q_ids = b_ids;
+    ma.q_off = b_off;
+    ma.q_k = b_k;
+    ma.q_stat = sc.qstat.as<int32_t>();
+    ma.theta32 = ix.theta32;
+    ma.out_ids = out_ids;
+    ma.out_scores = out_scores;
+    ma.out_count = out_count;
+    ma.perm = grouped ? sc.perm.as<int32_t>() : nullptr;
+    ma.n_docs = idx->n_docs;
+    ma.lists = (int32_t)G;
+    ma.k_max = k_max;
+    ma.q_first = 0;
+    BM25_HIP(launch_merge(KPL, dim3(n), q, ma));
+    return BM25_OK;
+  };
+  if (!graph) return enqueue(s);
+  // graph mode: the timing events (if enabled) bracket the whole graph
+  hipEvent_t tb = nullptr;
   rc = timed_begin(idx, s, &tb);
   if (rc != BM25_OK) return rc;
-  BM25_HIP(launch_gather(idx->params.store_dtype, W, QT, R, KPL,
-                         dim3((unsigned)((int64_t)n_tiles * G)), (size_t)lds, s, ga));
-  rc = timed_end(idx, s, tb);
+  // launch configuration: every grid size follows from n, n_tiles and G; the kernels and LDS
+  // sizes from the shape, list size, store type and grouping
+  const std::array<int64_t, 10> cfg = {(int64_t)n, (int64_t)n_tiles, G, lds, (int64_t)W,
+                                        (int64_t)QT, (int64_t)R, (int64_t)KPL,
+                                        (int64_t)idx->params.store_dtype, (int64_t)grouped};
+  rc = launch_as_graph(sc, s, cfg, enqueue);
   if (rc != BM25_OK) return rc;
-
-  MergeArgs ma;
-  ma.cand = sc.cand.as<uint64_t>();
-  ma.q_ids = b_ids;
-  ma.q_off = b_off;
-  ma.q_k = b_k;
-  ma.q_stat = sc.qstat.as<int32_t>();
-  ma.theta32 = ix.theta32;
-  ma.out_ids = out_ids;
-  ma.out_scores = out_scores;
-  ma.out_count = out_count;
-  ma.perm = grouped ? sc.perm.as<int32_t>() : nullptr;
-  ma.n_docs = idx->n_docs;
-  ma.lists = (int32_t)G;
-  ma.k_max = k_max;
-  ma.q_first = 0;
-  BM25_HIP(launch_merge(KPL, dim3(n), s, ma));
-  return BM25_OK;
+  return timed_end(idx, s, tb);
 }
 
 int search_plain_impl(bm25_index* idx, const int32_t* q_ids, const int64_t* q_off, int32_t n,
@@ -620,6 +692,25 @@ extern "C" int bm25_search_get_plan(const bm25_index* index, int32_t n_queries,
   plan->doc_groups = t.doc_groups;
   plan->query_order = t.query_order;
   plan->sparse_only = t.sparse_only;
+  return BM25_OK;
+}
+
+extern "C" int bm25_search_set_graphs(bm25_index* index, int32_t enable) {
+  clear_error();
+  if (!index) return set_error(BM25_E_INVAL, "index is NULL");
+  std::lock_guard<std::mutex> g(index->mu);
+  index->use_graphs = enable != 0;
+  return BM25_OK;
+}
+
+extern "C" int bm25_search_graph_stats(const bm25_index* index, int64_t* builds,
+                                       int64_t* updates) {
+  clear_error();
+  if (!index || !builds || !updates) return set_error(BM25_E_INVAL, "NULL argument");
+  bm25_index* idx = const_cast<bm25_index*>(index);
+  std::lock_guard<std::mutex> g(idx->mu);
+  *builds = idx->batch_scratch.graph_builds;
+  *updates = idx->batch_scratch.graph_updates;
   return BM25_OK;
 }
 

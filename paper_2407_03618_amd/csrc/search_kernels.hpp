@@ -956,7 +956,10 @@ __device__ __forceinline__ void accumulate_dense(const IndexView& ix, const Dens
 
 // Filters one accumulator row of a tile against the wave's current k-th key and offers the
 // survivors to the list. A plain FP32 comparison with the k-th score
-// rejects most values; only chunks with a candidate build 64-bit keys.
+// rejects most values; only chunks with a candidate build 64-bit keys. Every list sweeps its
+// documents in increasing id order, so a document that only ties the k-th score has a larger id
+// than the k-th key's and ranks below it: the comparison is strict (a list that holds fewer than
+// k keys has no threshold and takes everything).
 template <int KPL>
 __device__ __forceinline__ void select_row(float* rowp, int DT, int64_t t0, int64_t t1,
                                            TopList<KPL>& L, int cap, uint64_t& thr) {
@@ -965,7 +968,7 @@ __device__ __forceinline__ void select_row(float* rowp, int DT, int64_t t0, int6
   float thr_s = (thr == 0) ? -INFINITY : key_score(thr);
   for (int i = l; i < DT / 4; i += 64) {
     const float4 v4 = row[i];
-    const bool p = (v4.x >= thr_s) || (v4.y >= thr_s) || (v4.z >= thr_s) || (v4.w >= thr_s);
+    const bool p = (v4.x > thr_s) || (v4.y > thr_s) || (v4.z > thr_s) || (v4.w > thr_s);
     if (ballot(p)) {
       const int64_t db = t0 + 4 * i;
       const float vs[4] = {v4.x, v4.y, v4.z, v4.w};
@@ -989,14 +992,14 @@ __device__ __forceinline__ void select_row(float* rowp, int DT, int64_t t0, int6
   float thr_s = S.thr_score();
   for (int i = l; i < DT / 4; i += 64) {
     const float4 v4 = row[i];
-    const bool p = (v4.x >= thr_s) || (v4.y >= thr_s) || (v4.z >= thr_s) || (v4.w >= thr_s);
+    const bool p = (v4.x > thr_s) || (v4.y > thr_s) || (v4.z > thr_s) || (v4.w > thr_s);
     if (ballot(p)) {
       const int64_t db = t0 + 4 * i;
       const float vs[4] = {v4.x, v4.y, v4.z, v4.w};
 #pragma unroll
       for (int c = 0; c < 4; ++c) {
         const int64_t doc = db + c;
-        S.offer((doc < t1 && vs[c] >= thr_s) ? make_key(vs[c], (uint32_t)doc) : 0ull);
+        S.offer((doc < t1 && vs[c] > thr_s) ? make_key(vs[c], (uint32_t)doc) : 0ull);
       }
       thr_s = S.thr_score();
     }
@@ -1025,12 +1028,12 @@ __device__ __forceinline__ void select_regs(const float* v, int64_t first, int64
                                             StagedTopList<KPL>& S, float& thr_s) {
   bool p = false;
 #pragma unroll
-  for (int r = 0; r < R; ++r) p |= v[r] >= thr_s;
+  for (int r = 0; r < R; ++r) p |= v[r] > thr_s;
   if (ballot(p)) {
 #pragma unroll
     for (int r = 0; r < R; ++r) {
       const int64_t doc = first + r;
-      S.offer((doc < t1 && v[r] >= thr_s) ? make_key(v[r], (uint32_t)doc) : 0ull);
+      S.offer((doc < t1 && v[r] > thr_s) ? make_key(v[r], (uint32_t)doc) : 0ull);
     }
     thr_s = S.thr_score();
   }

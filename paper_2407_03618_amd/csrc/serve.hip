@@ -379,7 +379,7 @@ extern "C" int bm25_serve_destroy(bm25_server* sv) {
   for (auto& lp : sv->lanes) {
     if (lp->stream) {
       (void)hipStreamSynchronize(lp->stream);
-      if (lp->scratch.host_free) (void)hipEventDestroy(lp->scratch.host_free);
+      lp->scratch.release_handles();
       (void)hipStreamDestroy(lp->stream);
     }
   }

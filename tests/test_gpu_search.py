@@ -240,3 +240,60 @@ def test_empty_document_groups():
         ids, sc, cnt = _run(idx, q, 30, "batch")
         check_batch(ref, q.q_ids, q.q_offsets, q.k, ids, sc, cnt, RTOL["f16"], str(plan))
     torch.cuda.synchronize()
+
+
+def _sub_batch(q, idx, k=None):
+    parts = [q.query(i) for i in idx]
+    off = np.zeros(len(idx) + 1, np.int64)
+    off[1:] = np.cumsum([len(p) for p in parts])
+    kk = q.k[list(idx)].copy() if k is None else np.full(len(idx), k, np.int32)
+    return QueryBatch(np.concatenate(parts).astype(np.int32), off, kk)
+
+
+def test_graph_mode_matches_eager():
+    """Graph mode: batches of several sizes, k and tile orders run as one HIP graph launch each,
+    interleaved with eager searches and other device work on the same stream; a repeated batch
+    replays the kept graph (in-place update). Every graph result matches the oracle and the
+    eager result of the same batch."""
+    import torch
+    c = make_corpus(2, n_docs=60_000)
+    q = make_queries(2, n_queries=900, vocab=c.vocab, k=100)
+    ref = eager.build_index(c.tokens, c.doc_offsets, c.vocab, token_subset=np.unique(q.q_ids))
+    idx = _index(c, dtype="f16")
+    # (queries, k, tile order): grouped 300 / as given 300 / small / large k / ragged 777
+    cases = [(range(0, 300), 100, 0), (range(300, 600), 100, 0), (range(300, 600), 100, 0),
+             (range(0, 40), 10, 0), (range(100, 400), 100, 2), (range(0, 64), 1000, 0),
+             (range(123, 900), 100, 0), (range(123, 900), 100, 0)]
+    calls = 0
+    try:
+        for qs, k, order in cases:
+            qb = _sub_batch(q, list(qs), k)
+            if order:
+                plan = idx.get_plan(qb.n, 64, k)
+                plan["query_order"] = order
+                idx.set_plan(plan)
+            else:
+                idx.set_plan(None)
+            idx.set_graphs(False)
+            e_ids, e_sc, e_cnt = _run(idx, qb, k, "batch")
+            idx.set_graphs(True)
+            for rep in range(2):
+                # other device work between the replays
+                x = torch.arange(1 << 20, device="cuda", dtype=torch.float32)
+                assert float(x.sum().item()) == float((1 << 20) * ((1 << 20) - 1) // 2)
+                ids, sc, cnt = _run(idx, qb, k, "batch")
+                calls += 1
+                tag = f"graph {len(qs)}q k={k} order={order} rep={rep}"
+                check_batch(ref, qb.q_ids, qb.q_offsets, qb.k, ids, sc, cnt, RTOL["f16"], tag,
+                            sample=range(0, qb.n, 7))
+                assert np.array_equal(cnt, e_cnt), tag
+                # same ranked scores as the eager launch, within the storage tolerance
+                fin = np.isfinite(e_sc)
+                assert np.array_equal(fin, np.isfinite(sc)), tag
+                assert np.allclose(sc[fin], e_sc[fin], rtol=RTOL["f16"], atol=1e-6), tag
+    finally:
+        idx.set_graphs(False)
+        idx.set_plan(None)
+    st = idx.graph_stats()
+    assert st["builds"] + st["updates"] == calls, st
+    assert st["updates"] >= 1 and st["builds"] >= 1, st

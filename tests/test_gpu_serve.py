@@ -33,9 +33,20 @@ def _collect(server, n, k_stride):
     return out
 
 
-def test_alone_and_in_mix_agree(setup):
-    from paper_2407_03618_amd import Server
+@pytest.mark.parametrize("graphs", [False, True])
+def test_alone_and_in_mix_agree(setup, graphs):
+    """Each request alone and in a mix of micro-batches; with graphs, every micro-batch is one
+    HIP graph launch on its lane's stream."""
     c, q, idx, ref = setup
+    idx.set_graphs(graphs)
+    try:
+        _alone_and_in_mix(c, q, idx, ref)
+    finally:
+        idx.set_graphs(False)
+
+
+def _alone_and_in_mix(c, q, idx, ref):
+    from paper_2407_03618_amd import Server
     srv = Server(idx, hbm_budget_bytes=1 << 30, max_slots=4096, max_batch=16, max_k=1000,
                  n_streams=2)
     alone = []
