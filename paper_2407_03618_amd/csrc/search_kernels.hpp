@@ -648,7 +648,8 @@ __device__ __forceinline__ void init_cursors(const IndexView& ix, int e_lo, int 
 // wave's long rows are walked as one flat list, kChunksInFlight at a time: the loads of those
 // chunks are issued together (addresses are clamped inside the row instead of predicated, so no
 // load waits behind a branch), then each chunk's postings are added for every member query of
-// its entry. Rows without a skip table stream from their cursor until the first document >= t1.
+// its entry (a last group of fewer than kChunksInFlight chunks issues only the loads it needs).
+// Rows without a skip table stream from their cursor until the first document >= t1.
 constexpr int kChunksInFlight = 4;
 
 template <typename ST>
@@ -683,23 +684,24 @@ __device__ __forceinline__ void accumulate_tile(const IndexView& ix, const Entry
     }
     const int32_t base = incl - nch;
     const int32_t C = (int32_t)readlane((uint32_t)incl, 63);
-    for (int32_t c0 = 0; c0 < C; c0 += U) {
-      int32_t rel[U];
-      float sv[U];
-      int32_t memw[U];
+    // a group of UU chunks, all below C: the loads of the group first, then its additions
+    auto group = [&](auto uu, int32_t c0) {
+      constexpr int UU = decltype(uu)::value;
+      int32_t rel[UU];
+      float sv[UU];
+      int32_t memw[UU];
 #pragma unroll
-      for (int u = 0; u < U; ++u) {
+      for (int u = 0; u < UU; ++u) {
         const int32_t c = c0 + u;
-        const bool act = c < C;
         const uint64_t own = ballot(nch > 0 && base <= c);
-        const int src = act ? 63 - __builtin_clzll(own) : 0;
+        const int src = 63 - __builtin_clzll(own);
         const int32_t kk = c - (int32_t)readlane((uint32_t)base, src);
         const int64_t row = (int64_t)readlane64((uint64_t)rlo, src);
         const int32_t cs = (int32_t)readlane((uint32_t)cur, src);
         const int32_t ce = (int32_t)readlane((uint32_t)end, src);
-        memw[u] = act ? (int32_t)readlane((uint32_t)mw, src) : 0;
+        memw[u] = (int32_t)readlane((uint32_t)mw, src);
         const int32_t p = cs + 64 * kk + l;
-        const bool valid = act && p < ce;
+        const bool valid = p < ce;
         const int64_t off = row + (valid ? p : cs);
         const int32_t d = ix.indices[off];
         sv[u] = ST::load(data, off);
@@ -707,7 +709,7 @@ __device__ __forceinline__ void accumulate_tile(const IndexView& ix, const Entry
         rel[u] = (valid && r >= 0 && r < DT) ? r : -1;
       }
 #pragma unroll
-      for (int u = 0; u < U; ++u) {
+      for (int u = 0; u < UU; ++u) {
         // a single member comes inline with the entry; more (rare) from the LDS member copy
         const Members ms = decode_members((uint32_t)memw[u], mem_lds);
         if (ms.count > 0 && rel[u] >= 0)
@@ -721,6 +723,16 @@ __device__ __forceinline__ void accumulate_tile(const IndexView& ix, const Entry
           }
         }
       }
+    };
+    // full groups of U, then one group of the remaining 1..U-1 chunks (no idle load slots)
+    static_assert(U == 4, "the remainder cases below cover U - 1 = 3 chunks");
+    int32_t c0 = 0;
+    for (; c0 + U <= C; c0 += U) group(std::integral_constant<int, U>{}, c0);
+    switch (C - c0) {
+      case 3: group(std::integral_constant<int, 3>{}, c0); break;
+      case 2: group(std::integral_constant<int, 2>{}, c0); break;
+      case 1: group(std::integral_constant<int, 1>{}, c0); break;
+      default: break;
     }
     if (lid >= 0) cur = end;
     // rows without a skip table that have a posting in this tile
@@ -955,53 +967,75 @@ __device__ __forceinline__ void accumulate_dense(const IndexView& ix, const Dens
 }
 
 // Filters one accumulator row of a tile against the wave's current k-th key and offers the
-// survivors to the list. A plain FP32 comparison with the k-th score
-// rejects most values; only chunks with a candidate build 64-bit keys. Every list sweeps its
-// documents in increasing id order, so a document that only ties the k-th score has a larger id
-// than the k-th key's and ranks below it: the comparison is strict (a list that holds fewer than
-// k keys has no threshold and takes everything).
-template <int KPL>
-__device__ __forceinline__ void select_row(float* rowp, int DT, int64_t t0, int64_t t1,
+// survivors to the list. Each lane reads its NB float4 of a span together (the LDS reads are in
+// flight at once); a plain FP32 comparison of each float4's maximum with the k-th score rejects
+// most of them, and only float4 groups with a candidate build 64-bit keys. Every list sweeps
+// its documents in increasing id order, so a document that only ties the k-th score has a
+// larger id than the k-th key's and ranks below it: the comparison is strict (a list that holds
+// fewer than k keys has no threshold and takes everything).
+__device__ __forceinline__ float max4(const float4& v) {
+  return fmaxf(fmaxf(v.x, v.y), fmaxf(v.z, v.w));
+}
+
+template <int DT>
+struct RowSpan {
+  static_assert(DT % 256 == 0, "rows are read 64 float4 at a time");
+  static constexpr int NB = (DT / 256) < 2 ? (DT / 256) : 2;  // float4 per lane per span
+  static_assert((DT / 256) % NB == 0, "spans must tile the row");
+};
+
+template <int KPL, int DT>
+__device__ __forceinline__ void select_row(const float* rowp, int64_t t0, int64_t t1,
                                            TopList<KPL>& L, int cap, uint64_t& thr) {
+  constexpr int NB = RowSpan<DT>::NB;
   const int l = lane();
-  float4* row = reinterpret_cast<float4*>(rowp);
+  const float4* row = reinterpret_cast<const float4*>(rowp);
   float thr_s = (thr == 0) ? -INFINITY : key_score(thr);
-  for (int i = l; i < DT / 4; i += 64) {
-    const float4 v4 = row[i];
-    const bool p = (v4.x > thr_s) || (v4.y > thr_s) || (v4.z > thr_s) || (v4.w > thr_s);
-    if (ballot(p)) {
-      const int64_t db = t0 + 4 * i;
-      const float vs[4] = {v4.x, v4.y, v4.z, v4.w};
+  for (int s0 = 0; s0 < DT / 4; s0 += 64 * NB) {
+    float4 v4[NB];
 #pragma unroll
-      for (int c = 0; c < 4; ++c) {
-        const int64_t doc = db + c;
-        const uint64_t key = (doc < t1) ? make_key(vs[c], (uint32_t)doc) : 0ull;
-        L.offer(key, cap, thr);
+    for (int b = 0; b < NB; ++b) v4[b] = row[s0 + 64 * b + l];
+#pragma unroll
+    for (int b = 0; b < NB; ++b) {
+      if (ballot(max4(v4[b]) > thr_s)) {
+        const int64_t db = t0 + 4 * (s0 + 64 * b + l);
+        const float vs[4] = {v4[b].x, v4[b].y, v4[b].z, v4[b].w};
+#pragma unroll
+        for (int c = 0; c < 4; ++c) {
+          const int64_t doc = db + c;
+          const uint64_t key = (doc < t1) ? make_key(vs[c], (uint32_t)doc) : 0ull;
+          L.offer(key, cap, thr);
+        }
+        thr_s = (thr == 0) ? -INFINITY : key_score(thr);
       }
-      thr_s = (thr == 0) ? -INFINITY : key_score(thr);
     }
   }
 }
 
 // The same filter feeding a staged list (long lists, where one insertion per key is costly).
-template <int KPL>
-__device__ __forceinline__ void select_row(float* rowp, int DT, int64_t t0, int64_t t1,
+template <int KPL, int DT>
+__device__ __forceinline__ void select_row(const float* rowp, int64_t t0, int64_t t1,
                                            StagedTopList<KPL>& S) {
+  constexpr int NB = RowSpan<DT>::NB;
   const int l = lane();
-  float4* row = reinterpret_cast<float4*>(rowp);
+  const float4* row = reinterpret_cast<const float4*>(rowp);
   float thr_s = S.thr_score();
-  for (int i = l; i < DT / 4; i += 64) {
-    const float4 v4 = row[i];
-    const bool p = (v4.x > thr_s) || (v4.y > thr_s) || (v4.z > thr_s) || (v4.w > thr_s);
-    if (ballot(p)) {
-      const int64_t db = t0 + 4 * i;
-      const float vs[4] = {v4.x, v4.y, v4.z, v4.w};
+  for (int s0 = 0; s0 < DT / 4; s0 += 64 * NB) {
+    float4 v4[NB];
 #pragma unroll
-      for (int c = 0; c < 4; ++c) {
-        const int64_t doc = db + c;
-        S.offer((doc < t1 && vs[c] > thr_s) ? make_key(vs[c], (uint32_t)doc) : 0ull);
+    for (int b = 0; b < NB; ++b) v4[b] = row[s0 + 64 * b + l];
+#pragma unroll
+    for (int b = 0; b < NB; ++b) {
+      if (ballot(max4(v4[b]) > thr_s)) {
+        const int64_t db = t0 + 4 * (s0 + 64 * b + l);
+        const float vs[4] = {v4[b].x, v4[b].y, v4[b].z, v4[b].w};
+#pragma unroll
+        for (int c = 0; c < 4; ++c) {
+          const int64_t doc = db + c;
+          S.offer((doc < t1 && vs[c] > thr_s) ? make_key(vs[c], (uint32_t)doc) : 0ull);
+        }
+        thr_s = S.thr_score();
       }
-      thr_s = S.thr_score();
     }
   }
 }
@@ -1026,10 +1060,10 @@ __device__ __forceinline__ void put_lds(float* p, float* v) {
 template <int KPL, int R>
 __device__ __forceinline__ void select_regs(const float* v, int64_t first, int64_t t1,
                                             StagedTopList<KPL>& S, float& thr_s) {
-  bool p = false;
+  float mx = v[0];
 #pragma unroll
-  for (int r = 0; r < R; ++r) p |= v[r] > thr_s;
-  if (ballot(p)) {
+  for (int r = 1; r < R; ++r) mx = fmaxf(mx, v[r]);
+  if (ballot(mx > thr_s)) {
 #pragma unroll
     for (int r = 0; r < R; ++r) {
       const int64_t doc = first + r;
@@ -1155,9 +1189,9 @@ __global__ __launch_bounds__(W * 64) void k_gather(GatherArgs a) {
       const int ql = w * QPW + j;
       if (ql < nq) {
         if constexpr (kStaged)
-          select_row<KPL>(rows + ql * DT, DT, t0, t1, S[j]);
+          select_row<KPL, DT>(rows + ql * DT, t0, t1, S[j]);
         else
-          select_row<KPL>(rows + ql * DT, DT, t0, t1, L[j], cap[j], thr[j]);
+          select_row<KPL, DT>(rows + ql * DT, t0, t1, L[j], cap[j], thr[j]);
       }
     }
   }
