@@ -645,18 +645,26 @@ __device__ __forceinline__ void init_cursors(const IndexView& ix, int e_lo, int 
 //
 // Long rows take the tile's segment end from the skip table (tiles start and end on skip-block
 // boundaries, or at N). Their segments are cut into 64-posting chunks and the chunks of all the
-// wave's long rows are walked as one flat list, kChunksInFlight at a time: the loads of those
-// chunks are issued together (addresses are clamped inside the row instead of predicated, so no
-// load waits behind a branch), then each chunk's postings are added for every member query of
-// its entry (a last group of fewer than kChunksInFlight chunks issues only the loads it needs).
-// Rows without a skip table stream from their cursor until the first document >= t1.
-constexpr int kChunksInFlight = 4;
+// wave's long rows are walked as one flat list, U chunks at a time: the loads of those chunks
+// are issued together (addresses are clamped inside the row instead of predicated, so no load
+// waits behind a branch), then each chunk's postings are added for every member query of its
+// entry (a last group of fewer than U chunks issues only the loads it needs). U is 8 where the
+// registers allow it (short top-k lists), else 4. Rows without a skip table stream from their
+// cursor until the first document >= t1.
+template <int K, typename G>
+__device__ __forceinline__ void run_group_of(int32_t n, int32_t c0, G& group) {
+  if constexpr (K > 0) {
+    if (n == K)
+      group(std::integral_constant<int, K>{}, c0);
+    else
+      run_group_of<K - 1>(n, c0, group);
+  }
+}
 
-template <typename ST>
+template <typename ST, int U>
 __device__ __forceinline__ void accumulate_tile(const IndexView& ix, const EntryState& st,
                                                 int e_lo, int e_hi, const int32_t* mem_lds,
                                                 float* acc, int DT, int64_t t0, int64_t t1) {
-  constexpr int U = kChunksInFlight;
   const int l = lane();
   const typename ST::T* data = reinterpret_cast<const typename ST::T*>(ix.data);
   const int32_t t0i = (int32_t)t0, t1i = (int32_t)t1;
@@ -725,15 +733,9 @@ __device__ __forceinline__ void accumulate_tile(const IndexView& ix, const Entry
       }
     };
     // full groups of U, then one group of the remaining 1..U-1 chunks (no idle load slots)
-    static_assert(U == 4, "the remainder cases below cover U - 1 = 3 chunks");
     int32_t c0 = 0;
     for (; c0 + U <= C; c0 += U) group(std::integral_constant<int, U>{}, c0);
-    switch (C - c0) {
-      case 3: group(std::integral_constant<int, 3>{}, c0); break;
-      case 2: group(std::integral_constant<int, 2>{}, c0); break;
-      case 1: group(std::integral_constant<int, 1>{}, c0); break;
-      default: break;
-    }
+    run_group_of<U - 1>(C - c0, c0, group);
     if (lid >= 0) cur = end;
     // rows without a skip table that have a posting in this tile
     uint64_t pending = ballot(ve && lid < 0 && nd < t1i);
@@ -843,14 +845,15 @@ __device__ __forceinline__ void take_lds(float* p, float* v) {
 // (16 values per lane) and the next group's loads are issued before the current group's
 // additions.
 // acc += a * (half in the low / high 16 bits of h2), one FMA rounding: v_fma_mix_f32 widens the
-// FP16 operand inside the multiply-add, so no separate conversion is issued.
+// FP16 operand inside the multiply-add, so no separate conversion is issued. `a` must be the same
+// in every lane (it is read from a scalar register).
 __device__ __forceinline__ void fma_mix_lo(float& acc, float a, uint32_t h2) {
-  asm("v_fma_mix_f32 %0, %1, %2, %0 op_sel_hi:[0,1,0]" : "+v"(acc) : "v"(a), "v"(h2));
+  asm("v_fma_mix_f32 %0, %1, %2, %0 op_sel_hi:[0,1,0]" : "+v"(acc) : "s"(a), "v"(h2));
 }
 __device__ __forceinline__ void fma_mix_hi(float& acc, float a, uint32_t h2) {
   asm("v_fma_mix_f32 %0, %1, %2, %0 op_sel:[0,1,0] op_sel_hi:[0,1,0]"
       : "+v"(acc)
-      : "v"(a), "v"(h2));
+      : "s"(a), "v"(h2));
 }
 
 // accumulate_dense for FP16 rows: the stored halves stay packed in registers (R/2 words per
@@ -1182,7 +1185,7 @@ __global__ __launch_bounds__(W * 64) void k_gather(GatherArgs a) {
     for (int q = 0; q < QT; ++q)
       if (q < nq) put_lds<R>(rows + q * DT + first, acc[q]);
     __syncthreads();
-    accumulate_tile<ST>(ix, st, e_lo, e_hi, mem_lds, rows, DT, t0, t1);
+    accumulate_tile<ST, (KPL <= 2 ? 8 : 4)>(ix, st, e_lo, e_hi, mem_lds, rows, DT, t0, t1);
     __syncthreads();
 #pragma unroll
     for (int j = 0; j < QPW; ++j) {
@@ -1273,7 +1276,7 @@ __global__ __launch_bounds__(W * 64) void k_sweep(SweepArgs a) {
 
   for (int64_t t0 = d_lo; t0 < d_hi; t0 += DT) {
     const int64_t t1 = (t0 + DT < d_hi) ? t0 + DT : d_hi;
-    accumulate_tile<ST>(ix, st, 0, E, mem_lds, acc_sp, DT, t0, t1);
+    accumulate_tile<ST, 4>(ix, st, 0, E, mem_lds, acc_sp, DT, t0, t1);
     accumulate_dense<ST, 1, RS>(ix, dent, n_dense, t0 + l * RS, acc);
     float v[RS];
     take_lds<RS>(acc_sp + l * RS, v);
