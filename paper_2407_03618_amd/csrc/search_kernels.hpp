@@ -783,6 +783,111 @@ __device__ __forceinline__ void accumulate_tile(const IndexView& ix, const Entry
   }
 }
 
+// Batched form of accumulate_tile: no skip-table lookup per tile. Every entry keeps its cursor
+// and the document id at the cursor (nd), so the entries with a posting in [t0, t1) are those
+// with nd < t1. Each of them takes one 64-posting chunk from its cursor; the chunks of the wave's
+// entries are loaded U at a time, all loads of a group in flight together. The postings below t1
+// form a prefix of the chunk: they are added for every member query, the cursor moves past them
+// and nd becomes the first document id >= t1 (read from the same chunk). An entry whose 64
+// postings were all below t1 takes another chunk in a further pass.
+template <typename ST, int U>
+__device__ __forceinline__ void accumulate_tile_stream(const EntryState& st, const IndexView& ix,
+                                                       int e_lo, int e_hi,
+                                                       const int32_t* mem_lds, float* acc,
+                                                       int DT, int64_t t0, int64_t t1) {
+  const int l = lane();
+  const typename ST::T* data = reinterpret_cast<const typename ST::T*>(ix.data);
+  const int32_t t0i = (int32_t)t0, t1i = (int32_t)t1;
+  for (int g0 = e_lo; g0 < e_hi; g0 += 64) {
+    const int j = g0 + l;
+    const bool ve = j < e_hi;
+    int32_t nd = ve ? st.nd[j] : INT32_MAX;
+    uint64_t todo = ballot(nd < t1i);
+    if (todo == 0) continue;
+    int32_t cur = ve ? st.cur[j] : 0;
+    const int32_t len = ve ? st.len[j] : 0;
+    const int64_t rlo = ve ? st.row_lo[j] : 0;
+    const int32_t mw = ve ? st.mem[j] : 0;
+    uint64_t more = 0;  // entries whose chunk held only postings below t1
+    auto group = [&](auto uu, int32_t) {
+      constexpr int UU = decltype(uu)::value;
+      int src[UU];
+      int32_t dv[UU];
+      float sv[UU];
+      int32_t memw[UU];
+      int32_t csv[UU];
+      int32_t lnv[UU];
+#pragma unroll
+      for (int u = 0; u < UU; ++u) {
+        src[u] = __builtin_ctzll(todo);
+        todo &= todo - 1;
+        const int64_t row = (int64_t)readlane64((uint64_t)rlo, src[u]);
+        const int32_t cs = (int32_t)readlane((uint32_t)cur, src[u]);
+        const int32_t ln = (int32_t)readlane((uint32_t)len, src[u]);
+        memw[u] = (int32_t)readlane((uint32_t)mw, src[u]);
+        csv[u] = cs;
+        lnv[u] = ln;
+        const int32_t p = cs + l;
+        const bool in_row = p < ln;
+        const int64_t off = row + (in_row ? p : cs);  // cs < ln: the entry has a posting
+        const int32_t d = ix.indices[off];
+        sv[u] = ST::load(data, off);
+        dv[u] = in_row ? d : INT32_MAX;
+      }
+#pragma unroll
+      for (int u = 0; u < UU; ++u) {
+        const bool valid = dv[u] < t1i;
+        const int32_t r = dv[u] - t0i;
+        const int rel = (valid && r >= 0) ? r : -1;
+        // a single member comes inline with the entry; more (rare) from the LDS member copy
+        const Members ms = decode_members((uint32_t)memw[u], mem_lds);
+        if (ms.count > 0 && rel >= 0)
+          atomicAdd(acc + (int)(ms.first & 0xFFFFu) * DT + rel, sv[u] * (float)(ms.first >> 16));
+        if (ms.count > 1) {
+          const int32_t mem = (l < ms.count) ? mem_lds[ms.off + l] : 0;
+          for (int m = 1; m < ms.count; ++m) {
+            const uint32_t mm = readlane((uint32_t)mem, m);
+            const float v = sv[u] * (float)(mm >> 16);
+            if (rel >= 0) atomicAdd(acc + (int)(mm & 0xFFFFu) * DT + rel, v);
+          }
+        }
+        // postings are sorted by document: the ones below t1 are lanes 0 .. n-1. After a full
+        // chunk the entry either has postings left (another pass reads them and sets nd; until
+        // then nd only has to stay below t1) or is exhausted.
+        const int n = __popcll(ballot(valid));
+        int32_t next;
+        if (n < 64) {
+          next = (int32_t)readlane((uint32_t)dv[u], n);
+        } else if (csv[u] + 64 < lnv[u]) {
+          next = t0i;
+          more |= 1ull << src[u];
+        } else {
+          next = INT32_MAX;
+        }
+        if (l == src[u]) {
+          cur = csv[u] + n;
+          nd = next;
+        }
+      }
+    };
+    while (todo) {
+      while (todo) {
+        const int32_t cnt = __popcll(todo);
+        if (cnt >= U)
+          group(std::integral_constant<int, U>{}, 0);
+        else
+          run_group_of<U - 1>(cnt, 0, group);
+      }
+      todo = more;
+      more = 0;
+    }
+    if (ve) {
+      st.cur[j] = cur;
+      st.nd[j] = nd;
+    }
+  }
+}
+
 // Loads R consecutive stored scores (R * sizeof(T) bytes, aligned) and widens them to FP32.
 template <typename ST, int R>
 __device__ __forceinline__ void load_dense(const typename ST::T* p, float* v) {
@@ -1185,7 +1290,7 @@ __global__ __launch_bounds__(W * 64) void k_gather(GatherArgs a) {
     for (int q = 0; q < QT; ++q)
       if (q < nq) put_lds<R>(rows + q * DT + first, acc[q]);
     __syncthreads();
-    accumulate_tile<ST, (KPL <= 2 ? 8 : 4)>(ix, st, e_lo, e_hi, mem_lds, rows, DT, t0, t1);
+    accumulate_tile_stream<ST, (KPL <= 2 ? 8 : 4)>(st, ix, e_lo, e_hi, mem_lds, rows, DT, t0, t1);
     __syncthreads();
 #pragma unroll
     for (int j = 0; j < QPW; ++j) {
