@@ -97,11 +97,10 @@ struct PinnedBuf {
 };
 
 // Documents per skip block. Rows with at least kLongRow entries keep, for every block j, the
-// offset of their first entry whose document id is >= j * kSkipBlock, so a sweep that starts at
-// a block boundary finds its cursor with one load, and a document tile finds the end of its
-// segment of the row with one load (such rows join the batched 64-posting chunks; shorter rows
-// are streamed one at a time). 1024 entries: about 28k rows and 1 GB of table at 8.8M
-// documents, about 94k rows and 1.8 GB at 5M documents of 300 ids.
+// offset of their first entry whose document id is >= j * kSkipBlock, so a workgroup or a sweep
+// that starts at a block boundary finds its cursor in such a row with one load (shorter rows take
+// a binary search). About 28k rows and 1 GB of table at 8.8M documents, about 94k rows and
+// 1.8 GB at 5M documents of 300 ids.
 constexpr int64_t kSkipBlock = 1024;
 constexpr int64_t kLongRow = 1024;
 

@@ -640,17 +640,8 @@ __device__ __forceinline__ void init_cursors(const IndexView& ix, int e_lo, int 
   }
 }
 
-// Adds the postings of entries [e_lo, e_hi) that fall in the document tile [t0, t1) into the
-// accumulator rows acc[q * DT + (d - t0)] of their member queries.
-//
-// Long rows take the tile's segment end from the skip table (tiles start and end on skip-block
-// boundaries, or at N). Their segments are cut into 64-posting chunks and the chunks of all the
-// wave's long rows are walked as one flat list, U chunks at a time: the loads of those chunks
-// are issued together (addresses are clamped inside the row instead of predicated, so no load
-// waits behind a branch), then each chunk's postings are added for every member query of its
-// entry (a last group of fewer than U chunks issues only the loads it needs). U is 8 where the
-// registers allow it (short top-k lists), else 4. Rows without a skip table stream from their
-// cursor until the first document >= t1.
+// Runs group(integral_constant<int, n>, c0) for a run-time group size 1 <= n <= K, so that each
+// size is a compile-time unrolled group.
 template <int K, typename G>
 __device__ __forceinline__ void run_group_of(int32_t n, int32_t c0, G& group) {
   if constexpr (K > 0) {
@@ -661,135 +652,16 @@ __device__ __forceinline__ void run_group_of(int32_t n, int32_t c0, G& group) {
   }
 }
 
-template <typename ST, int U>
-__device__ __forceinline__ void accumulate_tile(const IndexView& ix, const EntryState& st,
-                                                int e_lo, int e_hi, const int32_t* mem_lds,
-                                                float* acc, int DT, int64_t t0, int64_t t1) {
-  const int l = lane();
-  const typename ST::T* data = reinterpret_cast<const typename ST::T*>(ix.data);
-  const int32_t t0i = (int32_t)t0, t1i = (int32_t)t1;
-  const bool at_end = t1 >= ix.n_docs;
-  const int64_t b1 = t1 / kSkipBlockDev;
-  for (int g0 = e_lo; g0 < e_hi; g0 += 64) {
-    const int j = g0 + l;
-    const bool ve = j < e_hi;
-    int32_t cur = ve ? st.cur[j] : 0;
-    const int32_t len = ve ? st.len[j] : 0;
-    const int32_t lid = ve ? st.lid[j] : -1;
-    int32_t nd = ve ? st.nd[j] : INT32_MAX;
-    const int64_t rlo = ve ? st.row_lo[j] : 0;
-    const int32_t mw = ve ? st.mem[j] : 0;
-    int32_t end = cur;
-    if (ve && lid >= 0)
-      end = at_end ? len : (int32_t)ix.skip[(int64_t)lid * (ix.n_blocks + 1) + b1];
-    // chunks of the long rows, flattened across the wave's entries
-    const int32_t nch = (lid >= 0 && end > cur) ? ((end - cur + 63) >> 6) : 0;
-    int32_t incl = nch;
-#pragma unroll
-    for (int o = 1; o < 64; o <<= 1) {
-      const int32_t y = (int32_t)bperm((uint32_t)incl, (l - o) & 63);
-      if (l >= o) incl += y;
-    }
-    const int32_t base = incl - nch;
-    const int32_t C = (int32_t)readlane((uint32_t)incl, 63);
-    // a group of UU chunks, all below C: the loads of the group first, then its additions
-    auto group = [&](auto uu, int32_t c0) {
-      constexpr int UU = decltype(uu)::value;
-      int32_t rel[UU];
-      float sv[UU];
-      int32_t memw[UU];
-#pragma unroll
-      for (int u = 0; u < UU; ++u) {
-        const int32_t c = c0 + u;
-        const uint64_t own = ballot(nch > 0 && base <= c);
-        const int src = 63 - __builtin_clzll(own);
-        const int32_t kk = c - (int32_t)readlane((uint32_t)base, src);
-        const int64_t row = (int64_t)readlane64((uint64_t)rlo, src);
-        const int32_t cs = (int32_t)readlane((uint32_t)cur, src);
-        const int32_t ce = (int32_t)readlane((uint32_t)end, src);
-        memw[u] = (int32_t)readlane((uint32_t)mw, src);
-        const int32_t p = cs + 64 * kk + l;
-        const bool valid = p < ce;
-        const int64_t off = row + (valid ? p : cs);
-        const int32_t d = ix.indices[off];
-        sv[u] = ST::load(data, off);
-        const int32_t r = d - t0i;
-        rel[u] = (valid && r >= 0 && r < DT) ? r : -1;
-      }
-#pragma unroll
-      for (int u = 0; u < UU; ++u) {
-        // a single member comes inline with the entry; more (rare) from the LDS member copy
-        const Members ms = decode_members((uint32_t)memw[u], mem_lds);
-        if (ms.count > 0 && rel[u] >= 0)
-          atomicAdd(acc + (int)(ms.first & 0xFFFFu) * DT + rel[u], sv[u] * (float)(ms.first >> 16));
-        if (ms.count > 1) {
-          const int32_t mem = (l < ms.count) ? mem_lds[ms.off + l] : 0;
-          for (int m = 1; m < ms.count; ++m) {
-            const uint32_t mm = readlane((uint32_t)mem, m);
-            const float v = sv[u] * (float)(mm >> 16);
-            if (rel[u] >= 0) atomicAdd(acc + (int)(mm & 0xFFFFu) * DT + rel[u], v);
-          }
-        }
-      }
-    };
-    // full groups of U, then one group of the remaining 1..U-1 chunks (no idle load slots)
-    int32_t c0 = 0;
-    for (; c0 + U <= C; c0 += U) group(std::integral_constant<int, U>{}, c0);
-    run_group_of<U - 1>(C - c0, c0, group);
-    if (lid >= 0) cur = end;
-    // rows without a skip table that have a posting in this tile
-    uint64_t pending = ballot(ve && lid < 0 && nd < t1i);
-    while (pending) {
-      const int src = __builtin_ctzll(pending);
-      pending &= pending - 1;
-      const int64_t row = (int64_t)readlane64((uint64_t)rlo, src);
-      const Members ms = decode_members(readlane((uint32_t)mw, src), mem_lds);
-      const int32_t mem = (ms.count > 1 && l < ms.count) ? mem_lds[ms.off + l] : 0;
-      const int32_t L = (int32_t)readlane((uint32_t)len, src);
-      int32_t c = (int32_t)readlane((uint32_t)cur, src);
-      int32_t ndnew;
-      while (true) {
-        const int32_t o = c + l;
-        const bool in_row = o < L;
-        const int64_t off = row + (in_row ? o : 0);
-        const int32_t dl = ix.indices[off];
-        const float s = ST::load(data, off);
-        const int32_t d = in_row ? dl : INT32_MAX;
-        const bool v = d < t1i;
-        const int32_t r = d - t0i;
-        const bool ok = v && r >= 0;
-        if (ok && ms.count > 0)
-          atomicAdd(acc + (int)(ms.first & 0xFFFFu) * DT + r, s * (float)(ms.first >> 16));
-        for (int m = 1; m < ms.count; ++m) {
-          const uint32_t mm = readlane((uint32_t)mem, m);
-          if (ok) atomicAdd(acc + (int)(mm & 0xFFFFu) * DT + r, s * (float)(mm >> 16));
-        }
-        const int n = __popcll(ballot(v));
-        c += n;
-        if (n < 64) {
-          ndnew = (int32_t)readlane((uint32_t)d, n);
-          break;
-        }
-      }
-      if (l == src) {
-        cur = c;
-        nd = ndnew;
-      }
-    }
-    if (ve) {
-      st.cur[j] = cur;
-      st.nd[j] = nd;
-    }
-  }
-}
-
-// Batched form of accumulate_tile: no skip-table lookup per tile. Every entry keeps its cursor
+// Adds the postings of entries [e_lo, e_hi) that fall in the document tile [t0, t1) into the
+// accumulator rows acc[q * DT + (d - t0)] of their member queries. Every entry keeps its cursor
 // and the document id at the cursor (nd), so the entries with a posting in [t0, t1) are those
-// with nd < t1. Each of them takes one 64-posting chunk from its cursor; the chunks of the wave's
-// entries are loaded U at a time, all loads of a group in flight together. The postings below t1
-// form a prefix of the chunk: they are added for every member query, the cursor moves past them
-// and nd becomes the first document id >= t1 (read from the same chunk). An entry whose 64
-// postings were all below t1 takes another chunk in a further pass.
+// with nd < t1: no lookup per tile. Each of them takes one 64-posting chunk from its cursor; the
+// chunks of the wave's entries are loaded U at a time, all loads of a group in flight together
+// (addresses are clamped inside the row instead of predicated, so no load waits behind a
+// branch), and a last group of fewer than U chunks issues only the loads it needs. The postings
+// below t1 form a prefix of the chunk: they are added for every member query, the cursor moves
+// past them and nd becomes the first document id >= t1 (read from the same chunk). An entry whose
+// 64 postings were all below t1 takes another chunk in a further pass.
 template <typename ST, int U>
 __device__ __forceinline__ void accumulate_tile_stream(const EntryState& st, const IndexView& ix,
                                                        int e_lo, int e_hi,
@@ -1381,7 +1253,7 @@ __global__ __launch_bounds__(W * 64) void k_sweep(SweepArgs a) {
 
   for (int64_t t0 = d_lo; t0 < d_hi; t0 += DT) {
     const int64_t t1 = (t0 + DT < d_hi) ? t0 + DT : d_hi;
-    accumulate_tile<ST, 4>(ix, st, 0, E, mem_lds, acc_sp, DT, t0, t1);
+    accumulate_tile_stream<ST, 4>(st, ix, 0, E, mem_lds, acc_sp, DT, t0, t1);
     accumulate_dense<ST, 1, RS>(ix, dent, n_dense, t0 + l * RS, acc);
     float v[RS];
     take_lds<RS>(acc_sp + l * RS, v);
