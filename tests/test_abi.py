@@ -57,3 +57,17 @@ def test_binding_fails_loudly_without_library(monkeypatch, tmp_path):
     monkeypatch.setattr(bm25, "LIB_PATH", str(tmp_path / "missing.so"))
     with pytest.raises(RuntimeError):
         bm25.load_library()
+
+
+def test_null_index_is_rejected_without_device_work(lib_path):
+    """Entry points taking an index reject NULL with BM25_E_INVAL and a message, before any
+    device call (runs on a host without a GPU)."""
+    from paper_2407_03618_amd import bm25
+    lib = bm25.load_library()
+    b = ctypes.c_int64()
+    u = ctypes.c_int64()
+    assert lib.bm25_search_set_graphs(None, 1) == bm25.E_INVAL
+    assert b"NULL" in lib.bm25_last_error()
+    assert lib.bm25_search_graph_stats(None, ctypes.byref(b), ctypes.byref(u)) == bm25.E_INVAL
+    assert lib.bm25_search_set_plan(None, None) == bm25.E_INVAL
+    assert lib.bm25_kernel_timing(None, 1) == bm25.E_INVAL
