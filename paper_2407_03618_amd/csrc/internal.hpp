@@ -103,6 +103,7 @@ struct PinnedBuf {
 // 1.8 GB at 5M documents of 300 ids.
 constexpr int64_t kSkipBlock = 1024;
 constexpr int64_t kLongRow = 1024;
+static_assert(kLongRow <= 64 * 64, "a row without a skip table is searched with 64 samples of 64");
 
 // Rows of tokens present in at least 1/kDenseFraction of the documents are also kept as dense
 // rows (one stored score per document, zero where the token is absent), at most kDenseBytes in

@@ -529,7 +529,8 @@ __global__ __launch_bounds__(kPlanThreads) void k_plan(IndexView ix, BatchView b
 // ------------------------------------------------------------------------------------------
 // Cursor search: offset inside the row of the first entry with document id >= d0.
 // Long rows read the skip table (d0 is a multiple of the skip block). Other rows (fewer than
-// 4096 entries) compare d0 against every 64th entry of the row, then scan one 64-entry chunk.
+// 1024 entries; up to 4096 would do) compare d0 against every 64th entry of the row, one per
+// lane, then scan one 64-entry chunk.
 // Whole wave, uniform arguments.
 __device__ __forceinline__ int32_t find_cursor(const IndexView& ix, int64_t row_lo, int32_t len,
                                                int32_t long_id, int64_t d0) {
@@ -556,10 +557,10 @@ __device__ __forceinline__ int32_t find_cursor(const IndexView& ix, int64_t row_
 
 // ------------------------------------------------------------------------------------------
 // Sweep state of the entries (query tokens) a wave walks through, structure of arrays in LDS:
-// static fields (row start, row length, skip-table row, members) and the dynamic cursor
-// (offset of the next unconsumed entry of the row) plus, for rows without a skip table, the
-// document id at the cursor (INT32_MAX past the end), so that a tile without postings of that
-// row costs no memory access.
+// static fields (row start, row length, skip-table row for placing the first cursor, members)
+// and the dynamic cursor (offset of the next unconsumed entry of the row) plus the document id
+// at the cursor (INT32_MAX past the end), so that a tile without postings of that row costs no
+// memory access.
 struct EntryState {
   int64_t* row_lo;
   int32_t* len;
