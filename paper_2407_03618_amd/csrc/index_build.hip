@@ -772,7 +772,8 @@ extern "C" int64_t bm25_index_device_bytes(const bm25_index* index) {
   for (auto* s : ss) {
     const bm25::DevBuf* sb[] = {&s->meta,      &s->wave_e0, &s->qstat, &s->entries,
                                 &s->members,   &s->cand,    &s->dense_ent, &s->dense_n,
-                                &s->perm,      &s->ids2,    &s->off2,  &s->k2};
+                                &s->perm,      &s->ids2,    &s->off2,  &s->k2,
+                                &s->tile_cost, &s->order};
     for (auto* b : sb) total += (int64_t)b->bytes;
   }
   return total;

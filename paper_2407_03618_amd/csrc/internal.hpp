@@ -124,6 +124,8 @@ struct SearchScratch {
   DevBuf cand;      // uint64 candidate lists
   DevBuf dense_ent; // planner dense entries (16 B per position)
   DevBuf dense_n;   // int32 per tile
+  DevBuf tile_cost; // float per tile: estimated gather work
+  DevBuf order;     // int32 per tile: gather order, longest first
   DevBuf perm;      // int32[n]: caller's index of each grouped query
   DevBuf ids2;      // grouped batch: token ids, offsets, k
   DevBuf off2;

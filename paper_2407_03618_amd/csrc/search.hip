@@ -398,6 +398,12 @@ int search_batch_impl(bm25_index* idx, const int32_t* q_ids, const int64_t* q_of
   BM25_RESERVE(sc.dense_ent, (size_t)std::max<int64_t>(info.positions, 1) * sizeof(DenseEntry));
   BM25_RESERVE(sc.dense_n, (size_t)n_tiles * 4);
   BM25_RESERVE(sc.cand, (size_t)n * G * KP * 8);
+  // longest tiles first when there is more than one round of workgroups to balance
+  const bool ordered = n_tiles > 1 && n_tiles <= kOrderMax;
+  if (ordered) {
+    BM25_RESERVE(sc.tile_cost, (size_t)n_tiles * 4);
+    BM25_RESERVE(sc.order, (size_t)n_tiles * 4);
+  }
   if (grouped) {
     BM25_RESERVE(sc.perm, (size_t)n * 4);
     BM25_RESERVE(sc.ids2, (size_t)std::max<int64_t>(info.positions, 1) * 4);
@@ -459,15 +465,22 @@ int search_batch_impl(bm25_index* idx, const int32_t* q_ids, const int64_t* q_of
     bv.members = sc.members.as<int32_t>();
     bv.dense_ent = sc.dense_ent.as<DenseEntry>();
     bv.dense_n = sc.dense_n.as<int32_t>();
+    bv.tile_cost = ordered ? sc.tile_cost.as<float>() : nullptr;
     bv.n_queries = n;
     bv.n_tiles = n_tiles;
 
     hipLaunchKernelGGL(k_plan, dim3(n_tiles), dim3(kPlanThreads), 0, q, ix, bv, W);
     BM25_HIP(hipGetLastError());
+    if (ordered) {
+      hipLaunchKernelGGL(k_order, dim3(1), dim3(kPlanThreads), 0, q, bv.tile_cost, n_tiles,
+                         sc.order.as<int32_t>());
+      BM25_HIP(hipGetLastError());
+    }
 
     GatherArgs ga;
     ga.ix = ix;
     ga.bv = bv;
+    ga.order = ordered ? sc.order.as<int32_t>() : nullptr;
     ga.cand = sc.cand.as<uint64_t>();
     ga.group_docs = group_docs;
     ga.n_groups = (int32_t)G;

@@ -79,9 +79,16 @@ struct BatchView {
   int32_t* members;        // q_local | mult << 16
   DenseEntry* dense_ent;   // per tile, at the tile's first position
   int32_t* dense_n;        // [n_tiles]: dense entries of each tile
+  float* tile_cost = nullptr;  // [n_tiles]: estimated gather work of each tile, if wanted
   int32_t n_queries;
   int32_t n_tiles;
 };
+
+// Relative gather work of a tile, in units of one sparse posting added for one query (from
+// timing the phases on the 8.8M-document batches): a dense row costs about as much as 218k
+// postings, a query's selection about as much as 127k.
+constexpr float kCostDenseRow = 218000.f;
+constexpr float kCostQuery = 127000.f;
 
 // ------------------------------------------------------------------------------------------
 // Planner: one workgroup per query tile.
@@ -428,6 +435,8 @@ __global__ __launch_bounds__(kPlanThreads) void k_plan(IndexView ix, BatchView b
   __syncthreads();
   const float total = sm.cost_sum[0] + sm.cost_sum[1] + sm.cost_sum[2] + sm.cost_sum[3];
   const float target = total / (float)W;
+  if (tid == 0 && bv.tile_cost)
+    bv.tile_cost[tile] = total + kCostDenseRow * (float)n_dent + kCostQuery * (float)nq;
   for (int u = tid; u < kPlanSort; u += kPlanThreads) {
     uint32_t parts = 0;
     if ((uint32_t)u < n_tok && !is_dense((uint32_t)u)) {
@@ -523,6 +532,31 @@ __global__ __launch_bounds__(kPlanThreads) void k_plan(IndexView ix, BatchView b
   __syncthreads();
   // 7. per-query status (errors were recorded in step 1; err[] was not touched since)
   for (int i = tid; i < nq; i += kPlanThreads) bv.q_stat[q0 + i] = (int32_t)sm.err[i];
+}
+
+// Tile order for the gather launch, longest first: workgroups are dispatched in block order, so
+// the tiles with the most work start first and short ones fill the end of the launch. One
+// workgroup; n_tiles <= kOrderMax. order[i] = tile with the i-th largest estimated cost (ties by
+// tile index).
+constexpr int kOrderMax = 4096;
+
+__global__ __launch_bounds__(kPlanThreads) void k_order(const float* cost, int32_t n_tiles,
+                                                          int32_t* order) {
+  __shared__ uint64_t key[kOrderMax];
+  int npow = 1;
+  while (npow < n_tiles) npow <<= 1;
+  for (int i = threadIdx.x; i < npow; i += kPlanThreads) {
+    uint64_t k = ~0ull;
+    if (i < n_tiles) {
+      const float c = cost[i] > 0.f ? cost[i] : 0.f;
+      const uint32_t cq = c < 4.0e9f ? (uint32_t)c : 0xFFFFFFFFu;
+      k = ((uint64_t)(~cq) << 32) | (uint32_t)i;
+    }
+    key[i] = k;
+  }
+  __syncthreads();
+  lds_bitonic_sort(key, npow);
+  for (int i = threadIdx.x; i < n_tiles; i += kPlanThreads) order[i] = (int32_t)(uint32_t)key[i];
 }
 #endif  // BM25_SEARCH_MAIN
 
@@ -1070,6 +1104,7 @@ __device__ __forceinline__ void select_regs(const float* v, int64_t first, int64
 struct GatherArgs {
   IndexView ix;
   BatchView bv;
+  const int32_t* order = nullptr;  // tile of each tile slot (longest first), or the identity
   uint64_t* cand;       // [n_queries][n_groups][KP]
   int64_t group_docs;   // multiple of the skip block and of DT
   int32_t n_groups;
@@ -1107,6 +1142,7 @@ __global__ __launch_bounds__(W * 64) void k_gather(GatherArgs a) {
 
   int tile, group;
   map_block(blockIdx.x, a.n_groups, tile, group);
+  if (a.order) tile = a.order[tile];
   const int w = threadIdx.x >> 6;
   const int l = lane();
   const BatchView& bv = a.bv;
