@@ -84,10 +84,11 @@ struct BatchView {
   int32_t n_tiles;
 };
 
-// Relative gather work of a tile, in units of one sparse posting added for one query (from
-// timing the phases on the 8.8M-document batches): a dense row costs about as much as 218k
-// postings, a query's selection about as much as 127k.
-constexpr float kCostDenseRow = 218000.f;
+// Relative gather work of a tile, in units of one sparse posting added for one query, used only
+// to order the launch. Timing the phases on the 8.8M-document batches gave about 218k postings
+// per dense row and 127k per query's selection; weighting a dense row twice that ordered the
+// launch best (its memory latency is exposed once per tile), and larger weights change nothing.
+constexpr float kCostDenseRow = 436000.f;
 constexpr float kCostQuery = 127000.f;
 
 // ------------------------------------------------------------------------------------------
