@@ -297,3 +297,18 @@ def test_graph_mode_matches_eager():
     st = idx.graph_stats()
     assert st["builds"] + st["updates"] == calls, st
     assert st["updates"] >= 1 and st["builds"] >= 1, st
+
+
+@pytest.mark.parametrize("n_queries", [9, 4096 * 8 + 100])
+def test_tile_order_small_and_past_limit(cfg0, n_queries):
+    """Longest-first tile order: a batch of two tiles (ordered) and one of more than 4096 tiles
+    (launched in plain tile order) both return every query's own results."""
+    c, _ = cfg0
+    q = make_queries(0, n_queries=n_queries, vocab=c.vocab, k=10)
+    ref = eager.build_index(c.tokens, c.doc_offsets, c.vocab, 1.5, 0.75, 0.0, "lucene")
+    idx = _index(c, dtype="f16")
+    ids, sc, cnt = _run(idx, q, 10, "batch")
+    step = max(1, n_queries // 300)
+    sample = list(range(0, n_queries, step)) + [n_queries - 1]
+    check_batch(ref, q.q_ids, q.q_offsets, q.k, ids, sc, cnt, RTOL["f16"], f"{n_queries} queries",
+                sample=sample)
