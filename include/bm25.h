@@ -21,7 +21,9 @@
  *   - "device" pointers are HIP device memory on the current device; "host" pointers are ordinary
  *     host memory. Every stream argument is a hipStream_t passed as void* (NULL = null stream).
  *   - The caller owns every buffer it passes. The library owns what it allocates (index arrays,
- *     scratch, server queues) and frees it in the matching *_free / *_destroy call.
+ *     scratch, server queues) and frees it in the matching *_free / *_destroy call. Device memory
+ *     comes from the caller's bm25_allocator when one is given to bm25_index_build (for example
+ *     PyTorch's caching allocator), else from hipMalloc.
  *   - Every int-returning call returns BM25_OK (0) on success or a negative bm25_status code; no
  *     C++ exception crosses the ABI. bm25_last_error() returns a thread-local message for the last
  *     failing call on the calling thread.
@@ -79,6 +81,20 @@ typedef struct {
   int32_t store_dtype;  /* enum bm25_dtype */
 } bm25_params;
 
+/* Device memory provider. alloc returns a device pointer of at least `bytes` bytes, aligned to 256
+ * bytes, usable on the current device, or NULL on failure (the library then returns
+ * BM25_E_NOMEM); free releases a pointer alloc returned. `stream` is the stream of the library
+ * call that allocates or frees (NULL = null stream): memory is used on that stream first, and the
+ * library synchronises with its own work on a buffer before handing it to free. ctx is passed
+ * through unchanged. Both callbacks may be called from the thread of any library call on the
+ * index or on a server over it, never from a library thread, and never concurrently for one
+ * index. */
+typedef struct {
+  void* (*alloc)(size_t bytes, void* stream, void* ctx);
+  void (*free)(void* ptr, void* stream, void* ctx);
+  void* ctx;
+} bm25_allocator;
+
 /* ---------------------------------------------------------------------------------------------
  * Index build (Section 2: "Calculation of BM25", "Eager index-time scoring",
  * "Efficient Matrix Sparsity"; Section 2.1 for shifted variants).
@@ -89,6 +105,10 @@ typedef struct {
  *             n_tokens. |D| is the number of ids of D, repeats included. Empty documents are
  *             allowed and count in N and in L_avg.
  * vocab_size  V: every id must lie in [0, V). A token with DF = 0 contributes 0 everywhere.
+ * allocator   device memory provider of the index: its arrays, the build's transient buffers
+ *             and the search scratch (grown on demand) all come from it, and bm25_index_free
+ *             returns them to it. NULL: hipMalloc / hipFree. The allocator struct is copied; its
+ *             ctx must stay valid until the index is freed.
  * stream      the build's kernels run on it; the call is synchronous (returns after the index is
  *             complete) because the number of stored pairs sizes the index arrays.
  * out         receives a new index that stays resident in device memory until bm25_index_free.
@@ -99,7 +119,7 @@ typedef struct {
  */
 int bm25_index_build(const int32_t* token_ids, int64_t n_tokens, const int64_t* doc_offsets,
                      int64_t n_docs, int32_t vocab_size, const bm25_params* params,
-                     void* stream, bm25_index** out);
+                     const bm25_allocator* allocator, void* stream, bm25_index** out);
 
 /* Sizes and corpus statistics of a built index; any output pointer may be NULL. sum_len is the
  * exact sum of |D| (int64) and l_avg = sum_len / n_docs (FP64). */
@@ -122,6 +142,13 @@ int bm25_index_export(const bm25_index* index, int64_t* indptr, int32_t* indices
 
 /* Device bytes held by the index (its arrays plus search scratch currently allocated). */
 int64_t bm25_index_device_bytes(const bm25_index* index);
+
+/* Range of the stored scores (fp16 / bf16 storage keeps fewer exponent bits than the FP32 value
+ * it rounds): counts, over all stored pairs, of values rounded to a subnormal of the storage
+ * type, of non-zero values rounded to zero, and of finite values rounded to infinity. All three
+ * are zero for FP32 storage unless the FP32 value itself is subnormal. Any pointer may be NULL. */
+int bm25_index_range_stats(const bm25_index* index, int64_t* subnormal, int64_t* flushed_to_zero,
+                           int64_t* overflow);
 
 /* Frees the index and everything it allocated. NULL is a no-op. Waits for work issued by the
  * library on the index's streams. */
@@ -235,18 +262,27 @@ int bm25_kernel_time_read(bm25_index* index, double* total_ms, int64_t* launches
  * Serving: continuous batching (Section 2, "Multi-threading", carried to a GPU request loop).
  *
  * The server keeps the index resident and runs a scheduler thread. Submitted queries wait in a
- * host queue; whenever a device slot frees up, the scheduler admits the waiting requests that
- * fit the slot count and the device accumulator budget into the next micro-batch and launches
- * it on one of n_streams streams, so micro-batches overlap on the device while later requests
- * keep arriving. A micro-batch holds one list-size class (k rounded up to a power of two, at
- * least 64): the oldest waiting request's, with the waiting requests of that class behind it.
- * Results are copied to pinned host memory and handed out by bm25_serve_poll.
+ * host queue; whenever one of the n_streams lanes is idle, the scheduler admits the waiting
+ * requests that fit the lane into the next micro-batch and launches it on the lane's stream, so
+ * micro-batches overlap on the device while later requests keep arriving. A micro-batch holds
+ * one list-size class (k rounded up to a power of two, at least 64): the oldest waiting
+ * request's, with the waiting requests of that class behind it.
  *
- * config: hbm_budget_bytes  device bytes the server may use for per-batch scratch (> 0)
+ * Memory: bm25_serve_create reserves the whole device budget at once, through the index's
+ * allocator, split evenly over the lanes; each lane's share holds its micro-batch's query ids,
+ * result rows and search scratch (planner tables, accumulator candidate lists). A request joins
+ * a micro-batch only while the scratch of the enlarged batch, computed for the launch shape the
+ * batch will run with, fits the lane's share, so nothing is allocated on the device after
+ * create. Pinned host staging is reserved at create too. Results are copied to pinned host
+ * memory and handed out by bm25_serve_poll.
+ *
+ * config: hbm_budget_bytes  device bytes reserved for the lanes (> 0); a lane's share must hold
+ *                           at least one request of the longest query and the largest k
  *         max_slots         requests in flight (queued + on the device), 1..1<<20
  *         max_batch         most requests in one micro-batch, 1..65536
  *         max_k             largest k a request may ask for, 1..BM25_MAX_K
- *         n_streams         concurrent micro-batches on the device, 1..8
+ *         n_streams         lanes: concurrent micro-batches on the device, 1..8
+ * BM25_E_NOMEM if the budget cannot be reserved or a lane's share is too small.
  */
 typedef struct {
   int64_t hbm_budget_bytes;
@@ -261,8 +297,8 @@ int bm25_serve_create(const bm25_index* index, const bm25_serve_config* config,
 
 /* Copies the query (host int32[q_len], 0 <= q_len <= BM25_MAX_QUERY_LEN) and returns at once with
  * a ticket. BM25_E_RANGE for an id outside [0, V); BM25_E_INVAL for k outside 1..max_k;
- * BM25_E_BUSY if max_slots requests are in flight; BM25_E_NOMEM if the request alone needs more
- * than the budget. */
+ * BM25_E_BUSY if max_slots requests are in flight; BM25_E_NOMEM if the request alone does not fit
+ * a lane's share of the budget. */
 int bm25_serve_submit(bm25_server* server, const int32_t* q_ids, int32_t q_len, int32_t k,
                       uint64_t* ticket);
 
@@ -273,21 +309,37 @@ int bm25_serve_submit(bm25_server* server, const int32_t* q_ids, int32_t q_len, 
 int bm25_serve_poll(bm25_server* server, uint64_t* tickets, int32_t* ids, float* scores,
                     int32_t* counts, int32_t max_results, int32_t k_stride, int64_t timeout_us);
 
-/* Server counters: requests submitted, completed, micro-batches launched, largest micro-batch,
- * and requests currently waiting for admission. Any pointer may be NULL. */
-int bm25_serve_stats(bm25_server* server, int64_t* submitted, int64_t* completed,
-                     int64_t* batches, int32_t* max_batch_seen, int32_t* waiting);
+/* Server counters since create. lane_busy_s sums, over lanes, the seconds each lane held a
+ * micro-batch (from launch to the reaping of its results); divided by the wall time it is the
+ * mean number of lanes in use. */
+typedef struct {
+  int64_t submitted;        /* requests accepted by bm25_serve_submit */
+  int64_t completed;        /* requests handed to the done queue */
+  int64_t batches;          /* micro-batches launched */
+  int64_t rejected_busy;    /* submits refused with BM25_E_BUSY (slot table full) */
+  int64_t rejected_nomem;   /* submits refused with BM25_E_NOMEM (request larger than a lane) */
+  int32_t max_batch_seen;   /* largest micro-batch */
+  int32_t waiting;          /* requests waiting for admission now */
+  int32_t lanes_busy;       /* lanes holding a micro-batch now */
+  int32_t max_lanes_busy;   /* most lanes busy at once */
+  double lane_busy_s;
+} bm25_serve_counters;
+
+int bm25_serve_stats(bm25_server* server, bm25_serve_counters* out);
 
 /* Open-loop load generator for latency measurement: a native thread submits request i (host
  * ids q_ids[q_offsets[i] .. q_offsets[i+1]), k[i]) at arrival_us[i] microseconds after the call
  * starts, while the calling thread polls. lat_us[i] receives completion time minus scheduled
- * arrival time (a request that waits for a free slot is charged from its scheduled arrival).
+ * arrival time (a request that waits for a free slot is charged from its scheduled arrival);
+ * queue_us[i] (optional) the part of it spent before admission into a micro-batch, so that
+ * lat_us[i] - queue_us[i] is the request's service time (device work, copies and hand-out).
  * Optional result rows (stride k_stride) and counts are stored per request. Tickets of this
  * replay must be consecutive: no other thread may submit to the server meanwhile. Returns the
  * number of completed requests or an error. */
 int bm25_serve_replay(bm25_server* server, const int32_t* q_ids, const int64_t* q_offsets,
                       const int32_t* k, const double* arrival_us, int32_t n, double* lat_us,
-                      int32_t* out_ids, float* out_scores, int32_t* out_count, int32_t k_stride);
+                      double* queue_us, int32_t* out_ids, float* out_scores, int32_t* out_count,
+                      int32_t k_stride);
 
 /* Stops the scheduler after the in-flight work drains and frees the server. Results not yet
  * polled are dropped. NULL is a no-op returning BM25_OK. */

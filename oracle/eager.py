@@ -161,6 +161,20 @@ def search(index: EagerIndex, query, k: int):
     return ids, b[ids]
 
 
+def search_partitioned(index: EagerIndex, query, k: int):
+    """Top-k the way the paper's implementation selects it (Section 2, "Top-k selection"):
+    partition the score vector around the k-th largest value, then sort only those k. Among
+    documents tied at the k-th score the partition keeps an unspecified subset, so the ids may
+    differ from ``search`` only there; the scores are the same. Used to time the paper's method."""
+    b = scores(index, query)
+    n = b.shape[0]
+    kk = min(int(k), n)
+    part = np.argpartition(-b, kk - 1)[:kk] if kk < n else np.arange(n)
+    order = np.lexsort((part, -b[part]))
+    ids = part[order]
+    return ids, b[ids]
+
+
 def search_batch(index: EagerIndex, q_ids, q_offsets, k):
     """Top-k of every query of a batch; ``k`` is a scalar or one value per query."""
     q_offsets = np.asarray(q_offsets, dtype=np.int64)

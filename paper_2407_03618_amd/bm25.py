@@ -1,14 +1,16 @@
 """Python binding of the gfx950 BM25S library (``libbm25_mi355x.so``) through ctypes.
 
 Argument marshalling only: every step of index build and search runs in the library's HIP
-kernels. PyTorch supplies device memory (tensors) and streams (``torch.cuda.current_stream()``).
-Importing this module does not need a GPU; creating an index does, and fails loudly if the
-library has not been built.
+kernels. PyTorch supplies device memory (tensors, and by default the index's own arrays and
+scratch through a ``bm25_allocator`` backed by PyTorch's caching allocator) and streams
+(``torch.cuda.current_stream()``). Importing this module does not need a GPU; creating an index
+does, and fails loudly if the library has not been built.
 """
 from __future__ import annotations
 
 import ctypes
 import os
+import sys
 from typing import Optional
 
 import numpy as np
@@ -29,7 +31,7 @@ OK, E_INVAL, E_RANGE, E_NOMEM, E_BUSY, E_HIP, E_STATE, E_TIMEOUT = 0, -1, -2, -3
 # every symbol include/bm25.h declares
 EXPORTED = (
     "bm25_index_build", "bm25_index_info", "bm25_index_export", "bm25_index_device_bytes",
-    "bm25_index_free", "bm25_search_batch", "bm25_search_plain", "bm25_search_set_plan",
+    "bm25_index_range_stats", "bm25_index_free", "bm25_search_batch", "bm25_search_plain", "bm25_search_set_plan",
     "bm25_search_get_plan", "bm25_search_set_graphs", "bm25_search_graph_stats",
     "bm25_autotune", "bm25_kernel_timing", "bm25_kernel_time_read",
     "bm25_serve_create", "bm25_serve_submit", "bm25_serve_poll", "bm25_serve_stats",
@@ -57,6 +59,50 @@ class ServeConfig(ctypes.Structure):
                 ("n_streams", ctypes.c_int32)]
 
 
+class ServeCounters(ctypes.Structure):
+    _fields_ = [("submitted", ctypes.c_int64), ("completed", ctypes.c_int64),
+                ("batches", ctypes.c_int64), ("rejected_busy", ctypes.c_int64),
+                ("rejected_nomem", ctypes.c_int64), ("max_batch_seen", ctypes.c_int32),
+                ("waiting", ctypes.c_int32), ("lanes_busy", ctypes.c_int32),
+                ("max_lanes_busy", ctypes.c_int32), ("lane_busy_s", ctypes.c_double)]
+
+
+ALLOC_FN = ctypes.CFUNCTYPE(ctypes.c_void_p, ctypes.c_size_t, ctypes.c_void_p, ctypes.c_void_p)
+FREE_FN = ctypes.CFUNCTYPE(None, ctypes.c_void_p, ctypes.c_void_p, ctypes.c_void_p)
+
+
+class Allocator(ctypes.Structure):
+    _fields_ = [("alloc", ALLOC_FN), ("free", FREE_FN), ("ctx", ctypes.c_void_p)]
+
+
+class TorchAllocator:
+    """bm25_allocator backed by PyTorch's caching allocator on one device: the library's device
+    memory shows up in torch.cuda.memory_allocated() and is reused by PyTorch once freed."""
+
+    def __init__(self, device: int):
+        self.device = int(device)
+        self._alloc = ALLOC_FN(self._alloc_cb)
+        self._free = FREE_FN(self._free_cb)
+        self.struct = Allocator(self._alloc, self._free, None)
+        self.live = {}  # pointer -> bytes of the allocations the library holds
+
+    def _alloc_cb(self, nbytes, stream, ctx):
+        # the raw stream handle (0 = null stream) is the stream the library uses the memory on
+        try:
+            torch = _torch()
+            p = int(torch.cuda.caching_allocator_alloc(int(nbytes), self.device,
+                                                       int(stream or 0)))
+        except Exception:  # out of memory: the library reports BM25_E_NOMEM
+            return None
+        self.live[p] = int(nbytes)
+        return p
+
+    def _free_cb(self, ptr, stream, ctx):
+        if ptr:
+            self.live.pop(int(ptr), None)
+            _torch().cuda.caching_allocator_delete(int(ptr))
+
+
 class BM25Error(RuntimeError):
     def __init__(self, code: int, msg: str):
         super().__init__(f"bm25 error {code}: {msg}")
@@ -77,7 +123,8 @@ def load_library() -> ctypes.CDLL:
     L = ctypes.CDLL(LIB_PATH)
     vp, i32, i64, dbl = ctypes.c_void_p, ctypes.c_int32, ctypes.c_int64, ctypes.c_double
     P = ctypes.POINTER
-    L.bm25_index_build.argtypes = [vp, i64, vp, i64, i32, P(Params), vp, P(vp)]
+    L.bm25_index_build.argtypes = [vp, i64, vp, i64, i32, P(Params), P(Allocator), vp, P(vp)]
+    L.bm25_index_range_stats.argtypes = [vp, P(i64), P(i64), P(i64)]
     L.bm25_index_info.argtypes = [vp, P(i64), P(i32), P(i64), P(i64), P(dbl), P(Params)]
     L.bm25_index_export.argtypes = [vp, vp, vp, vp, vp, vp, vp, vp, vp]
     L.bm25_index_device_bytes.argtypes = [vp]
@@ -96,8 +143,8 @@ def load_library() -> ctypes.CDLL:
     L.bm25_serve_create.argtypes = [vp, P(ServeConfig), P(vp)]
     L.bm25_serve_submit.argtypes = [vp, vp, i32, i32, P(ctypes.c_uint64)]
     L.bm25_serve_poll.argtypes = [vp, vp, vp, vp, vp, i32, i32, i64]
-    L.bm25_serve_stats.argtypes = [vp, P(i64), P(i64), P(i64), P(i32), P(i32)]
-    L.bm25_serve_replay.argtypes = [vp, vp, vp, vp, vp, i32, vp, vp, vp, vp, i32]
+    L.bm25_serve_stats.argtypes = [vp, P(ServeCounters)]
+    L.bm25_serve_replay.argtypes = [vp, vp, vp, vp, vp, i32, vp, vp, vp, vp, vp, i32]
     L.bm25_serve_destroy.argtypes = [vp]
     L.bm25_copy_bytes.argtypes = [vp, vp, i64, vp]
     L.bm25_last_error.argtypes = []
@@ -146,7 +193,10 @@ class Index:
     """A BM25S index resident in device memory, built by the library's HIP kernels."""
 
     def __init__(self, token_ids, doc_offsets, vocab: int, k1: float = 1.5, b: float = 0.75,
-                 delta: float = 0.0, variant="lucene", dtype="f32", stream=None):
+                 delta: float = 0.0, variant="lucene", dtype="f32", stream=None,
+                 allocator: str = "torch"):
+        """allocator: "torch" (the index's device memory comes from PyTorch's caching allocator)
+        or None (the library calls hipMalloc)."""
         torch = _torch()
         L = load_library()
         if not (token_ids.is_cuda and doc_offsets.is_cuda):
@@ -158,9 +208,14 @@ class Index:
         var = VARIANTS[variant] if isinstance(variant, str) else int(variant)
         dt = DTYPES[dtype] if isinstance(dtype, str) else int(dtype)
         self.params = Params(float(k1), float(b), float(delta), var, dt)
+        if allocator not in ("torch", None):
+            raise ValueError("allocator must be 'torch' or None")
+        # the callbacks must outlive the index: they are called again by free()
+        self._allocator = TorchAllocator(token_ids.device.index) if allocator else None
         h = ctypes.c_void_p()
         rc = L.bm25_index_build(_ptr(token_ids), token_ids.numel(), _ptr(doc_offsets),
                                 doc_offsets.numel() - 1, int(vocab), ctypes.byref(self.params),
+                                ctypes.byref(self._allocator.struct) if self._allocator else None,
                                 _stream_ptr(stream), ctypes.byref(h))
         _check(rc)
         self._h = h
@@ -185,6 +240,10 @@ class Index:
             self._h = None
 
     def __del__(self):
+        # at interpreter exit the allocator callbacks can no longer run: leave the memory to
+        # the process teardown
+        if sys.is_finalizing():
+            return
         try:
             self.free()
         except Exception:
@@ -192,6 +251,13 @@ class Index:
 
     def device_bytes(self) -> int:
         return int(load_library().bm25_index_device_bytes(self._h))
+
+    def range_stats(self) -> dict:
+        """Stored values rounded to a subnormal, from non-zero to zero, and to infinity."""
+        a, b, c = ctypes.c_int64(), ctypes.c_int64(), ctypes.c_int64()
+        _check(load_library().bm25_index_range_stats(self._h, ctypes.byref(a), ctypes.byref(b),
+                                                     ctypes.byref(c)))
+        return {"subnormal": a.value, "flushed_to_zero": b.value, "overflow": c.value}
 
     def export(self, stream=None) -> dict:
         """Device copies of indptr, indices, tf, df, idf, theta and data."""
@@ -346,15 +412,15 @@ class Server:
         return [(int(tickets[i]), int(counts[i]), ids[i], scores[i]) for i in range(rc)]
 
     def stats(self) -> dict:
-        s, c, b = ctypes.c_int64(), ctypes.c_int64(), ctypes.c_int64()
-        m, w = ctypes.c_int32(), ctypes.c_int32()
-        _check(load_library().bm25_serve_stats(self._h, ctypes.byref(s), ctypes.byref(c),
-                                               ctypes.byref(b), ctypes.byref(m), ctypes.byref(w)))
-        return dict(submitted=s.value, completed=c.value, batches=b.value,
-                    max_batch=m.value, waiting=w.value)
+        c = ServeCounters()
+        _check(load_library().bm25_serve_stats(self._h, ctypes.byref(c)))
+        return {f: getattr(c, f) for f, _ in ServeCounters._fields_}
 
-    def replay(self, q_ids, q_offsets, k, arrival_us, k_stride: Optional[int] = None):
-        """Open-loop replay; returns (latency_us[n], ids[n, k_stride], scores, counts)."""
+    def replay(self, q_ids, q_offsets, k, arrival_us, k_stride: Optional[int] = None,
+               keep_results: bool = True):
+        """Open-loop replay; returns (latency_us[n], queue_us[n], ids[n, k_stride], scores,
+        counts). queue_us is the wait before admission into a micro-batch. With
+        keep_results=False the result rows are not kept (ids and scores are None)."""
         q = _host_i32(q_ids)
         off = _host_i64(q_offsets)
         n = off.shape[0] - 1
@@ -362,15 +428,17 @@ class Server:
         arr = np.ascontiguousarray(np.asarray(arrival_us, dtype=np.float64))
         ks = int(k_stride or self.max_k)
         lat = np.full(n, np.nan)
-        ids = np.zeros((n, ks), np.int32)
-        scores = np.zeros((n, ks), np.float32)
+        queue = np.full(n, np.nan)
+        ids = np.zeros((n, ks), np.int32) if keep_results else None
+        scores = np.zeros((n, ks), np.float32) if keep_results else None
         counts = np.zeros(n, np.int32)
-        rc = load_library().bm25_serve_replay(self._h, q.ctypes.data if q.size else None,
-                                              off.ctypes.data, kk.ctypes.data, arr.ctypes.data,
-                                              n, lat.ctypes.data, ids.ctypes.data,
-                                              scores.ctypes.data, counts.ctypes.data, ks)
+        rc = load_library().bm25_serve_replay(
+            self._h, q.ctypes.data if q.size else None, off.ctypes.data, kk.ctypes.data,
+            arr.ctypes.data, n, lat.ctypes.data, queue.ctypes.data,
+            ids.ctypes.data if keep_results else None,
+            scores.ctypes.data if keep_results else None, counts.ctypes.data, ks)
         _check(rc)
-        return lat, ids, scores, counts
+        return lat, queue, ids, scores, counts
 
     def close(self) -> None:
         if getattr(self, "_h", None):
@@ -378,7 +446,10 @@ class Server:
             self._h = None
 
     def __del__(self):
+        if sys.is_finalizing():
+            return
         try:
             self.close()
         except Exception:
             pass
+

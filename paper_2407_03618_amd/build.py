@@ -48,7 +48,7 @@ def _compile(unit, extra, verbose):
     src = os.path.join(CSRC, unit)
     tag = "_".join(x.split("=")[-1] for x in extra if x.startswith("-DBM25_ST_SUFFIX"))
     obj = os.path.join(BUILD_DIR, os.path.splitext(unit)[0] + (f"_{tag}" if tag else "") + ".o")
-    cmd = [_hipcc(), *COMMON, *extra, "-c", src, "-o", obj]
+    cmd = [_hipcc(), *COMMON, "-I", BUILD_DIR, *extra, "-c", src, "-o", obj]
     if verbose:
         print(" ".join(cmd), flush=True)
     r = subprocess.run(cmd, capture_output=True, text=True)

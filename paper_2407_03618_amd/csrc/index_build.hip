@@ -18,6 +18,7 @@
 #include <cstring>
 #include <memory>
 #include <utility>
+#include <type_traits>
 #include <vector>
 
 #include "device.hpp"
@@ -403,6 +404,30 @@ __device__ __forceinline__ float stored_factor(float tf, float len, const ScoreP
   }
 }
 
+// Range class of a stored value v (the FP32 score x rounded to the storage type): bit 0 when v is
+// subnormal in that type, bit 1 when x != 0 rounded to zero, bit 2 when finite x became infinite.
+template <typename ST>
+__device__ __forceinline__ uint32_t range_class(float x, typename ST::T v) {
+  float back;
+  float min_normal;
+  if constexpr (sizeof(typename ST::T) == 4) {
+    back = v;
+    min_normal = 1.17549435e-38f;  // 2^-126
+  } else if constexpr (std::is_same<ST, F16>::value) {
+    back = __half2float(v);
+    min_normal = 6.103515625e-05f;  // 2^-14
+  } else {
+    back = __uint_as_float((uint32_t)v << 16);
+    min_normal = 1.17549435e-38f;
+  }
+  const float a = fabsf(back);
+  uint32_t c = 0;
+  if (a != 0.0f && a < min_normal) c |= 1u;
+  if (back == 0.0f && x != 0.0f) c |= 2u;
+  if (isinf(back) && !isinf(x)) c |= 4u;
+  return c;
+}
+
 template <typename ST>
 __global__ __launch_bounds__(256) void k_score(const uint64_t* __restrict__ uniq,
                                                const uint32_t* __restrict__ starts, int64_t nnz,
@@ -410,17 +435,29 @@ __global__ __launch_bounds__(256) void k_score(const uint64_t* __restrict__ uniq
                                                const double* __restrict__ idf, ScoreParams p,
                                                int32_t* __restrict__ indices,
                                                int32_t* __restrict__ tf_out,
-                                               typename ST::T* __restrict__ data) {
+                                               typename ST::T* __restrict__ data,
+                                               unsigned long long* __restrict__ range) {
   const int64_t j = (int64_t)blockIdx.x * blockDim.x + threadIdx.x;
-  if (j >= nnz) return;
-  const uint64_t key = uniq[j];
-  const uint32_t t = (uint32_t)(key >> 32);
-  const uint32_t d = (uint32_t)key;
-  const uint32_t tf = starts[j + 1] - starts[j];
-  indices[j] = (int32_t)d;
-  tf_out[j] = (int32_t)tf;
-  const float w = (float)idf[t];
-  data[j] = ST::store(w * stored_factor((float)tf, (float)doclen[d], p));
+  uint32_t cls = 0;
+  if (j < nnz) {
+    const uint64_t key = uniq[j];
+    const uint32_t t = (uint32_t)(key >> 32);
+    const uint32_t d = (uint32_t)key;
+    const uint32_t tf = starts[j + 1] - starts[j];
+    indices[j] = (int32_t)d;
+    tf_out[j] = (int32_t)tf;
+    const float w = (float)idf[t];
+    const float x = w * stored_factor((float)tf, (float)doclen[d], p);
+    const typename ST::T v = ST::store(x);
+    data[j] = v;
+    cls = range_class<ST>(x, v);
+  }
+  // one atomic per wave and class that occurs (almost never)
+#pragma unroll
+  for (int c = 0; c < 3; ++c) {
+    const uint64_t m = ballot((cls >> c) & 1u);
+    if (m != 0 && lane() == 0) atomicAdd(range + c, (unsigned long long)__popcll(m));
+  }
 }
 
 // Skip table of long rows: skip[lid][b] = offset inside the row of the first entry whose
@@ -482,7 +519,8 @@ using namespace bm25;
 
 extern "C" int bm25_index_build(const int32_t* token_ids, int64_t n_tokens,
                                 const int64_t* doc_offsets, int64_t n_docs, int32_t vocab_size,
-                                const bm25_params* params, void* stream, bm25_index** out) {
+                                const bm25_params* params, const bm25_allocator* allocator,
+                                void* stream, bm25_index** out) {
   clear_error();
   if (!out) return set_error(BM25_E_INVAL, "out is NULL");
   *out = nullptr;
@@ -503,9 +541,18 @@ extern "C" int bm25_index_build(const int32_t* token_ids, int64_t n_tokens,
   if (P.store_dtype < BM25_F32 || P.store_dtype > BM25_BF16)
     return set_error(BM25_E_INVAL, "unknown store dtype %d", P.store_dtype);
   if (n_tokens == 0) return set_error(BM25_E_INVAL, "sum of |D| is 0: L_avg is undefined");
+  if (allocator && (!allocator->alloc || !allocator->free))
+    return set_error(BM25_E_INVAL, "allocator callbacks are NULL");
 
   hipStream_t s = (hipStream_t)stream;
   std::unique_ptr<bm25_index> idx(new bm25_index());
+  if (allocator) {
+    idx->alloc.fn = *allocator;
+    idx->alloc.custom = true;
+  }
+  idx->alloc.stream = s;
+  idx->bind_alloc();
+  const Alloc* al = &idx->alloc;
   BM25_HIP(hipGetDevice(&idx->device));
   idx->n_docs = n_docs;
   idx->n_tokens = n_tokens;
@@ -523,9 +570,11 @@ extern "C" int bm25_index_build(const int32_t* token_ids, int64_t n_tokens,
   } while (0)
 
   // 1. validation, |D|, sum |D|
-  DevBuf st;
-  BM25_ALLOC(st, sizeof(BuildStatus));
-  BM25_HIP(hipMemsetAsync(st.ptr, 0, sizeof(BuildStatus), s));
+  DevBuf st(al);
+  BM25_ALLOC(st, sizeof(BuildStatus) + 4 * sizeof(unsigned long long));
+  BM25_HIP(hipMemsetAsync(st.ptr, 0, sizeof(BuildStatus) + 4 * sizeof(unsigned long long), s));
+  unsigned long long* range_dev = reinterpret_cast<unsigned long long*>(st.as<uint8_t>() +
+                                                                         sizeof(BuildStatus));
   BM25_ALLOC(idx->doclen, (size_t)N * 4);
   {
     int64_t work = std::max(N, T);
@@ -545,7 +594,7 @@ extern "C" int bm25_index_build(const int32_t* token_ids, int64_t n_tokens,
   idx->l_avg = (double)idx->sum_len / (double)N;
 
   // 2. keys
-  DevBuf ka, kb;
+  DevBuf ka(al), kb(al);
   BM25_ALLOC(ka, (size_t)T * 8);
   BM25_ALLOC(kb, (size_t)T * 8);
   hipLaunchKernelGGL(k_make_keys, dim3((unsigned)std::min<int64_t>(grid_for(N * 64, 256), 65536)),
@@ -557,7 +606,7 @@ extern "C" int bm25_index_build(const int32_t* token_ids, int64_t n_tokens,
   const int passes = (tbits + 7) / 8;
   const int64_t nblk = (T + kRadixBlockItems - 1) / kRadixBlockItems;
   const int64_t hn = nblk * 1024;
-  DevBuf hist, tmp;
+  DevBuf hist(al), tmp(al);
   BM25_ALLOC(hist, (size_t)hn * 4);
   const int64_t nrb = (T + kRleBlockItems - 1) / kRleBlockItems;
   BM25_ALLOC(tmp, (size_t)std::max({scan_tmp_elems(hn), scan_tmp_elems(T), scan_tmp_elems(V),
@@ -579,7 +628,7 @@ extern "C" int bm25_index_build(const int32_t* token_ids, int64_t n_tokens,
   hist.release();
 
   // 4. run-length encoding: distinct (t, D) pairs and TF
-  DevBuf counts, total;
+  DevBuf counts(al), total(al);
   BM25_ALLOC(counts, (size_t)nrb * 4 * 4);
   BM25_ALLOC(total, 16);
   hipLaunchKernelGGL(k_rle_count, dim3((unsigned)nrb), dim3(256), 0, s, src, T,
@@ -588,7 +637,7 @@ extern "C" int bm25_index_build(const int32_t* token_ids, int64_t n_tokens,
   BM25_HIP(scan_exclusive<uint32_t>(counts.as<uint32_t>(), counts.as<uint32_t>(), nrb * 4,
                                     tmp.as<uint32_t>(), total.as<uint32_t>(), s));
   uint64_t* uniq = dst;  // the other sort buffer
-  DevBuf starts;
+  DevBuf starts(al);
   BM25_ALLOC(starts, ((size_t)T + 1) * 4);
   hipLaunchKernelGGL(k_rle_write, dim3((unsigned)nrb), dim3(256), 0, s, src, T,
                      counts.as<uint32_t>(), uniq, starts.as<uint32_t>());
@@ -611,7 +660,7 @@ extern "C" int bm25_index_build(const int32_t* token_ids, int64_t n_tokens,
   hipLaunchKernelGGL(k_indptr, dim3(grid_for(nnz + 1, 256)), dim3(256), 0, s, uniq, nnz, V,
                      idx->indptr.as<int64_t>());
   BM25_HIP(hipGetLastError());
-  DevBuf is_long, long_excl;
+  DevBuf is_long(al), long_excl(al);
   BM25_ALLOC(is_long, (size_t)V * 4);
   BM25_ALLOC(long_excl, (size_t)V * 4);
   hipLaunchKernelGGL(k_df_idf, dim3(grid_for(V, 256)), dim3(256), 0, s,
@@ -643,27 +692,32 @@ extern "C" int bm25_index_build(const int32_t* token_ids, int64_t n_tokens,
         hipLaunchKernelGGL(k_score<F32>, dim3(g), dim3(256), 0, s, uniq, starts.as<uint32_t>(),
                            nnz, idx->doclen.as<int32_t>(), idx->idf.as<double>(), sp,
                            idx->indices.as<int32_t>(), idx->tf.as<int32_t>(),
-                           idx->data.as<float>());
+                           idx->data.as<float>(), range_dev);
         break;
       case BM25_F16:
         hipLaunchKernelGGL(k_score<F16>, dim3(g), dim3(256), 0, s, uniq, starts.as<uint32_t>(),
                            nnz, idx->doclen.as<int32_t>(), idx->idf.as<double>(), sp,
                            idx->indices.as<int32_t>(), idx->tf.as<int32_t>(),
-                           idx->data.as<__half>());
+                           idx->data.as<__half>(), range_dev);
         break;
       default:
         hipLaunchKernelGGL(k_score<BF16>, dim3(g), dim3(256), 0, s, uniq, starts.as<uint32_t>(),
                            nnz, idx->doclen.as<int32_t>(), idx->idf.as<double>(), sp,
                            idx->indices.as<int32_t>(), idx->tf.as<int32_t>(),
-                           idx->data.as<uint16_t>());
+                           idx->data.as<uint16_t>(), range_dev);
     }
     BM25_HIP(hipGetLastError());
   }
 
   // 7. skip table of long rows
   uint32_t n_long = 0;
+  unsigned long long range_h[3] = {0, 0, 0};
   BM25_HIP(hipMemcpyAsync(&n_long, total.as<uint32_t>() + 1, 4, hipMemcpyDeviceToHost, s));
+  BM25_HIP(hipMemcpyAsync(range_h, range_dev, sizeof(range_h), hipMemcpyDeviceToHost, s));
   BM25_HIP(hipStreamSynchronize(s));
+  idx->range_subnormal = (int64_t)range_h[0];
+  idx->range_to_zero = (int64_t)range_h[1];
+  idx->range_overflow = (int64_t)range_h[2];
   idx->n_long = n_long;
   idx->n_blocks = (N + kSkipBlock - 1) / kSkipBlock;
   BM25_ALLOC(idx->skip, (size_t)std::max<int64_t>(1, (int64_t)n_long * (idx->n_blocks + 1)) * 4);
@@ -721,7 +775,18 @@ extern "C" int bm25_index_build(const int32_t* token_ids, int64_t n_tokens,
     BM25_HIP(hipStreamSynchronize(s));
   }
 #undef BM25_ALLOC
+  idx->alloc.stream = nullptr;
   *out = idx.release();
+  return BM25_OK;
+}
+
+extern "C" int bm25_index_range_stats(const bm25_index* index, int64_t* subnormal,
+                                      int64_t* flushed_to_zero, int64_t* overflow) {
+  clear_error();
+  if (!index) return set_error(BM25_E_INVAL, "index is NULL");
+  if (subnormal) *subnormal = index->range_subnormal;
+  if (flushed_to_zero) *flushed_to_zero = index->range_to_zero;
+  if (overflow) *overflow = index->range_overflow;
   return BM25_OK;
 }
 
@@ -768,20 +833,14 @@ extern "C" int64_t bm25_index_device_bytes(const bm25_index* index) {
                                 &index->dense_id, &index->dense_rank, &index->dense};
   int64_t total = 0;
   for (auto* b : bufs) total += (int64_t)b->bytes;
-  const bm25::SearchScratch* ss[] = {&index->batch_scratch, &index->plain_scratch};
-  for (auto* s : ss) {
-    const bm25::DevBuf* sb[] = {&s->meta,      &s->wave_e0, &s->qstat, &s->entries,
-                                &s->members,   &s->cand,    &s->dense_ent, &s->dense_n,
-                                &s->perm,      &s->ids2,    &s->off2,  &s->k2,
-                                &s->tile_cost, &s->order};
-    for (auto* b : sb) total += (int64_t)b->bytes;
-  }
+  total += (int64_t)index->batch_scratch.arena.bytes + (int64_t)index->plain_scratch.arena.bytes;
   return total;
 }
 
 extern "C" void bm25_index_free(bm25_index* index) {
   if (!index) return;
   (void)hipDeviceSynchronize();
+  index->alloc.stream = nullptr;
   for (auto& ev : index->timing_events) {
     (void)hipEventDestroy(ev.first);
     (void)hipEventDestroy(ev.second);

@@ -33,16 +33,45 @@ struct HipError {
     }                                                                              \
   } while (0)
 
-// Device buffer owned by the library.
+// Source of an index's device memory: the caller's allocator (bm25_allocator) or hipMalloc.
+// `stream` is handed to the caller's callbacks; it is the stream of the call that allocates.
+struct Alloc {
+  bm25_allocator fn{};
+  bool custom = false;
+  hipStream_t stream = nullptr;
+
+  hipError_t alloc(void** p, size_t n) const {
+    if (!custom) return hipMalloc(p, n);
+    *p = fn.alloc(n, (void*)stream, fn.ctx);
+    if (!*p) return hipErrorOutOfMemory;
+    if (((uintptr_t)*p & 255u) != 0) {  // the documented alignment is part of the contract
+      fn.free(*p, (void*)stream, fn.ctx);
+      *p = nullptr;
+      return hipErrorInvalidValue;
+    }
+    return hipSuccess;
+  }
+  void free(void* p) const {
+    if (!custom) (void)hipFree(p);
+    else fn.free(p, (void*)stream, fn.ctx);
+  }
+};
+
+// Device buffer owned by the library, allocated through `al` (hipMalloc when null).
 struct DevBuf {
   void* ptr = nullptr;
   size_t bytes = 0;
+  const Alloc* al = nullptr;
   DevBuf() = default;
+  explicit DevBuf(const Alloc* a) : al(a) {}
   DevBuf(const DevBuf&) = delete;
   DevBuf& operator=(const DevBuf&) = delete;
   ~DevBuf() { release(); }
   void release() {
-    if (ptr) (void)hipFree(ptr);
+    if (ptr) {
+      if (al) al->free(ptr);
+      else (void)hipFree(ptr);
+    }
     ptr = nullptr;
     bytes = 0;
   }
@@ -51,7 +80,7 @@ struct DevBuf {
     if (n <= bytes) return hipSuccess;
     release();
     size_t want = n < 256 ? 256 : n;
-    hipError_t e = hipMalloc(&ptr, want);
+    hipError_t e = al ? al->alloc(&ptr, want) : hipMalloc(&ptr, want);
     if (e != hipSuccess) {
       ptr = nullptr;
       return e;
@@ -112,42 +141,47 @@ constexpr int64_t kDenseFraction = 16;
 constexpr int64_t kDenseBytes = 4ll << 30;
 constexpr int64_t kDensePad = 4096;
 
-// Per-batch device scratch of the search path (grown on demand, reused across calls).
-// `meta` mirrors the pinned staging block written by the host planner:
-//   int64 q_off[n+1] | int32 q_k[n] | int32 tile_q0[n_tiles+1] | int64 tile_e0[n_tiles+1]
+// Per-call device scratch of the search path: one arena, carved per call (layout in search.hip).
+// The host plan (query offsets, k, tile bounds) is staged in host memory and copied to the
+// arena's first region.
 struct SearchScratch {
-  DevBuf meta;
-  DevBuf wave_e0;   // int32[n_tiles * (W+1)]
-  DevBuf qstat;     // int32[n]
-  DevBuf entries;   // planner entries
-  DevBuf members;   // int32 per position
-  DevBuf cand;      // uint64 candidate lists
-  DevBuf dense_ent; // planner dense entries (16 B per position)
-  DevBuf dense_n;   // int32 per tile
-  DevBuf tile_cost; // float per tile: estimated gather work
-  DevBuf order;     // int32 per tile: gather order, longest first
-  DevBuf perm;      // int32[n]: caller's index of each grouped query
-  DevBuf ids2;      // grouped batch: token ids, offsets, k
-  DevBuf off2;
-  DevBuf k2;
-  PinnedBuf host;   // staging for the host-side plan
-  hipEvent_t host_free = nullptr;  // the staging buffer may be rewritten once this has fired
+  DevBuf arena;                 // owned arena, grown on demand
+  uint8_t* fixed = nullptr;     // or an arena lent by the caller (server lane, static scratch)
+  size_t fixed_bytes = 0;
+  PinnedBuf host;               // pinned staging of the host plan, grown on demand
+  uint8_t* host_fixed = nullptr;  // or lent staging (pageable: the copy is staged by HIP)
+  size_t host_fixed_bytes = 0;
+  bool no_alloc = false;        // no allocation of any kind: no events, graphs or timing
+  hipEvent_t host_free = nullptr;  // the pinned staging may be rewritten once this has fired
+  hipEvent_t done = nullptr;    // recorded after the last call's launches, on that call's stream
+  hipStream_t last_stream = nullptr;  // stream of the last call (valid once done was recorded)
+  bool used = false;
   // graph mode: launches are recorded on cap_stream (capture only, nothing runs there) and the
-  // instantiated graph is kept for the next batch, updated in place while its topology holds
+  // instantiated graphs are kept for the next batches, updated in place while their topology
+  // holds. Two are kept and used in turn, so a graph is only updated once its own previous
+  // launch (two batches back) has finished, never the launch still in flight.
   hipStream_t cap_stream = nullptr;
-  hipGraphExec_t graph_exec = nullptr;
-  std::array<int64_t, 10> graph_cfg{};  // launch configuration the kept graph was captured with
+  hipGraphExec_t graph_exec[2] = {nullptr, nullptr};
+  hipEvent_t graph_done[2] = {nullptr, nullptr};
+  std::array<int64_t, 10> graph_cfg[2]{};  // launch configuration each graph was captured with
+  int graph_next = 0;
   int64_t graph_builds = 0;    // instantiations
   int64_t graph_updates = 0;   // in-place updates
 
   // Destroys the events, streams and graphs (device buffers free themselves).
   void release_handles() {
-    if (graph_exec) (void)hipGraphExecDestroy(graph_exec);
+    for (int i = 0; i < 2; ++i) {
+      if (graph_exec[i]) (void)hipGraphExecDestroy(graph_exec[i]);
+      if (graph_done[i]) (void)hipEventDestroy(graph_done[i]);
+      graph_exec[i] = nullptr;
+      graph_done[i] = nullptr;
+    }
     if (cap_stream) (void)hipStreamDestroy(cap_stream);
     if (host_free) (void)hipEventDestroy(host_free);
-    graph_exec = nullptr;
+    if (done) (void)hipEventDestroy(done);
     cap_stream = nullptr;
     host_free = nullptr;
+    done = nullptr;
   }
 };
 
@@ -163,6 +197,7 @@ struct TileShape {
 }  // namespace bm25
 
 struct bm25_index {
+  bm25::Alloc alloc;  // declared first: outlives every buffer below
   int device = 0;
   int64_t n_docs = 0;
   int64_t n_tokens = 0;
@@ -205,7 +240,20 @@ struct bm25_index {
   double timing_ms = 0.0;
   int64_t timing_launches = 0;
 
+  // stored values rounded to a subnormal, from non-zero to zero, and to infinity
+  int64_t range_subnormal = 0;
+  int64_t range_to_zero = 0;
+  int64_t range_overflow = 0;
+
   std::mutex mu;
+
+  // Every device buffer of the index and its scratch takes memory from `alloc`.
+  void bind_alloc() {
+    bm25::DevBuf* bufs[] = {&indptr, &indices, &tf, &data, &df, &idf, &theta, &theta32,
+                            &doclen, &long_id, &skip, &dense_id, &dense_rank, &dense,
+                            &batch_scratch.arena, &plain_scratch.arena};
+    for (auto* b : bufs) b->al = &alloc;
+  }
 };
 
 namespace bm25 {
@@ -216,8 +264,15 @@ int search_batch_impl(bm25_index* idx, const int32_t* q_ids_dev, const int64_t* 
                       float* out_scores, int32_t* out_count, hipStream_t stream,
                       SearchScratch& scratch, const TileShape* force);
 
-size_t search_scratch_bytes(const bm25_index* idx, int32_t n, int64_t positions, int32_t k_max,
-                            const TileShape& shape);
+// Launch shape bm25_search_batch uses for a batch (fixed plan, tuned plan or automatic).
+TileShape batch_shape(const bm25_index* idx, int32_t n, int32_t max_qlen, int32_t k_max);
+
+// Device arena bytes and host staging bytes a batch of n queries with `positions` ids (the
+// longest holding max_qlen) and lists for k_max needs under bm25_search_batch's launch shape;
+// an upper bound of what search_batch_impl carves.
+size_t batch_arena_bytes(const bm25_index* idx, int32_t n, int64_t positions, int32_t max_qlen,
+                         int32_t k_max);
+size_t batch_staging_bytes(int32_t n);
 
 TileShape choose_shape(const bm25_index* idx, int32_t n, int32_t max_qlen, int32_t k_max);
 

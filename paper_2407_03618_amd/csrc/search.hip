@@ -7,6 +7,7 @@
 #include <chrono>
 #include <cmath>
 #include <cstring>
+#include <mutex>
 #include <vector>
 
 #include "internal.hpp"
@@ -202,6 +203,8 @@ static T* carve(uint8_t*& p, size_t count) {
   return r;
 }
 
+// Host plan of one call, staged in host memory and copied to the first region of the arena.
+// Tile arrays have room for n + 1 tiles (every tile holds at least one query).
 struct Staged {
   int64_t* q_off;
   int32_t* q_k;
@@ -210,13 +213,67 @@ struct Staged {
 };
 
 // Lays out (q_off, q_k, tile_q0, tile_e0) in `base`; returns the byte size.
-static size_t stage_layout(uint8_t* base, int32_t n, int32_t n_tiles, Staged& s) {
+static size_t stage_layout(uint8_t* base, int32_t n, Staged& s) {
   uint8_t* p = base;
   s.q_off = carve<int64_t>(p, (size_t)n + 1);
   s.q_k = carve<int32_t>(p, (size_t)n);
-  s.tile_q0 = carve<int32_t>(p, (size_t)n_tiles + 1);
-  s.tile_e0 = carve<int64_t>(p, (size_t)n_tiles + 1);
+  s.tile_q0 = carve<int32_t>(p, (size_t)n + 2);
+  s.tile_e0 = carve<int64_t>(p, (size_t)n + 2);
   return (size_t)(p - base) + 16;
+}
+
+size_t batch_staging_bytes(int32_t n) {
+  Staged s;
+  return stage_layout(nullptr, n, s) + 64;
+}
+
+// Regions of one call inside the search arena, each 256-byte aligned.
+struct ArenaNeed {
+  int32_t n = 0;            // queries
+  int32_t n_tiles = 0;      // planner tiles (one per query in the per-query form)
+  int32_t waves = 1;        // waves the planner deals entries to
+  int64_t ent = 0;          // planner entry slots
+  int64_t positions = 0;    // query ids of the call
+  int64_t cand_keys = 0;    // candidate list keys
+  bool ordered = false;     // tile cost and launch order
+  bool grouped = false;     // grouped copy of the batch
+};
+
+struct ArenaLayout {
+  size_t meta = 0, wave_e0 = 0, qstat = 0, entries = 0, members = 0, dense_ent = 0, dense_n = 0,
+         cand = 0, tile_cost = 0, order = 0, perm = 0, ids2 = 0, off2 = 0, k2 = 0;
+  size_t total = 0;
+};
+
+static ArenaLayout arena_layout(const ArenaNeed& a) {
+  ArenaLayout L;
+  size_t off = 0;
+  auto take = [&](size_t bytes) {
+    const size_t o = off;
+    off = (off + std::max<size_t>(bytes, 1) + 255) & ~(size_t)255;
+    return o;
+  };
+  const size_t pos = (size_t)std::max<int64_t>(a.positions, 1);
+  L.meta = take(batch_staging_bytes(a.n));
+  L.wave_e0 = take((size_t)a.n_tiles * (a.waves + 1) * 4);
+  L.qstat = take((size_t)a.n * 4);
+  L.entries = take((size_t)std::max<int64_t>(a.ent, 1) * sizeof(Entry));
+  L.members = take(pos * 4);
+  L.dense_ent = take(pos * sizeof(DenseEntry));
+  L.dense_n = take((size_t)a.n_tiles * 4);
+  L.cand = take((size_t)a.cand_keys * 8);
+  if (a.ordered) {
+    L.tile_cost = take((size_t)a.n_tiles * 4);
+    L.order = take((size_t)a.n_tiles * 4);
+  }
+  if (a.grouped) {
+    L.perm = take((size_t)a.n * 4);
+    L.ids2 = take(pos * 4);
+    L.off2 = take(((size_t)a.n + 1) * 8);
+    L.k2 = take((size_t)a.n * 4);
+  }
+  L.total = off;
+  return L;
 }
 
 #define BM25_RESERVE(buf, bytes)                                                       \
@@ -227,27 +284,71 @@ static size_t stage_layout(uint8_t* base, int32_t n, int32_t n_tiles, Staged& s)
                        (long long)(bytes), hipGetErrorString(e_));                     \
   } while (0)
 
-// Copies the host plan (offsets, k, tiles) to the device through the pinned staging block.
-static int upload_plan(SearchScratch& sc, hipStream_t s, int32_t n, int32_t n_tiles,
-                       const int64_t* q_off, const int32_t* k, int32_t k_max,
-                       const std::vector<int32_t>& tile_q0, const std::vector<int64_t>& tile_e0,
-                       Staged& dev) {
+// Host staging for the plan of a call of n queries: the lent buffer (pageable; hipMemcpyAsync
+// consumes it before returning), else the pinned buffer once the previous upload has read it.
+static int acquire_staging(SearchScratch& sc, int32_t n, uint8_t** host) {
+  const size_t bytes = batch_staging_bytes(n);
+  if (sc.host_fixed) {
+    if (bytes > sc.host_fixed_bytes)
+      return set_error(BM25_E_NOMEM, "a batch of %d queries needs %zu bytes of host staging, "
+                       "%zu are available", n, bytes, sc.host_fixed_bytes);
+    *host = sc.host_fixed;
+    return BM25_OK;
+  }
   if (!sc.host_free) BM25_HIP(hipEventCreateWithFlags(&sc.host_free, hipEventDisableTiming));
   else BM25_HIP(hipEventSynchronize(sc.host_free));
-  Staged hs;
-  const size_t bytes = stage_layout(nullptr, n, n_tiles, hs) + 64;
   BM25_RESERVE(sc.host, bytes);
-  BM25_RESERVE(sc.meta, bytes);
-  stage_layout(sc.host.as<uint8_t>(), n, n_tiles, hs);
-  stage_layout(sc.meta.as<uint8_t>(), n, n_tiles, dev);
+  *host = sc.host.as<uint8_t>();
+  return BM25_OK;
+}
+
+// Device arena of `need` bytes: the lent one, or the owned one grown once the previous call's
+// work on it has finished.
+static int acquire_arena(SearchScratch& sc, size_t need, uint8_t** base) {
+  if (sc.fixed) {
+    if (need > sc.fixed_bytes)
+      return set_error(BM25_E_NOMEM, "the call needs %zu bytes of search scratch, %zu are "
+                       "available", need, sc.fixed_bytes);
+    *base = sc.fixed;
+    return BM25_OK;
+  }
+  if (need > sc.arena.bytes && sc.done) BM25_HIP(hipEventSynchronize(sc.done));
+  BM25_RESERVE(sc.arena, need);
+  *base = sc.arena.as<uint8_t>();
+  return BM25_OK;
+}
+
+// Orders this call's use of the scratch after the previous call's: on the same stream the
+// stream order does it; on another stream the call waits for the previous call's last launch.
+static int scratch_begin(SearchScratch& sc, hipStream_t s) {
+  if (sc.no_alloc) return BM25_OK;
+  if (!sc.done) BM25_HIP(hipEventCreateWithFlags(&sc.done, hipEventDisableTiming));
+  else if (sc.used && sc.last_stream != s) BM25_HIP(hipStreamWaitEvent(s, sc.done, 0));
+  return BM25_OK;
+}
+
+static int scratch_end(SearchScratch& sc, hipStream_t s) {
+  if (!sc.done) return BM25_OK;
+  BM25_HIP(hipEventRecord(sc.done, s));
+  sc.last_stream = s;
+  sc.used = true;
+  return BM25_OK;
+}
+
+// Copies the staged host plan into the arena's meta region.
+static int upload_plan(SearchScratch& sc, hipStream_t s, int32_t n, const uint8_t* host,
+                       uint8_t* meta) {
+  const size_t bytes = batch_staging_bytes(n);
+  BM25_HIP(hipMemcpyAsync(meta, host, bytes, hipMemcpyHostToDevice, s));
+  if (!sc.host_fixed) BM25_HIP(hipEventRecord(sc.host_free, s));
+  return BM25_OK;
+}
+
+static void stage_queries(const Staged& hs, const int64_t* q_off, const int32_t* k, int32_t n,
+                          int32_t k_max) {
   std::memcpy(hs.q_off, q_off, ((size_t)n + 1) * 8);
   if (k) std::memcpy(hs.q_k, k, (size_t)n * 4);
   else for (int32_t i = 0; i < n; ++i) hs.q_k[i] = k_max;
-  std::memcpy(hs.tile_q0, tile_q0.data(), ((size_t)n_tiles + 1) * 4);
-  std::memcpy(hs.tile_e0, tile_e0.data(), ((size_t)n_tiles + 1) * 8);
-  BM25_HIP(hipMemcpyAsync(sc.meta.ptr, sc.host.ptr, bytes, hipMemcpyHostToDevice, s));
-  BM25_HIP(hipEventRecord(sc.host_free, s));
-  return BM25_OK;
 }
 
 static int timed_begin(bm25_index* idx, hipStream_t s, hipEvent_t* b) {
@@ -268,14 +369,19 @@ static int timed_end(bm25_index* idx, hipStream_t s, hipEvent_t b) {
 }
 
 // Records the launches that `enqueue` issues into a HIP graph on the scratch's capture stream
-// (capture only: nothing runs there) and launches the graph on `s`. The executable graph is kept;
-// the next batch with the same launch configuration `cfg` (same kernels, grid and LDS sizes: only
-// pointers and scalar arguments differ) updates it in place, any other is instantiated anew. The
-// captured sequence holds kernel launches only, no memset or copy nodes.
+// (capture only: nothing runs there) and launches the graph on `s`. The executable graphs are
+// kept (two, used in turn); the next batch with the same launch configuration `cfg` (same
+// kernels, grid and LDS sizes: only pointers and scalar arguments differ) updates one in place,
+// any other is instantiated anew. A kept graph is updated or destroyed only after its own last
+// launch has finished. The captured sequence holds kernel launches only, no memset or copy nodes.
 template <typename F>
 static int launch_as_graph(SearchScratch& sc, hipStream_t s, const std::array<int64_t, 10>& cfg,
                            F& enqueue) {
   if (!sc.cap_stream) BM25_HIP(hipStreamCreateWithFlags(&sc.cap_stream, hipStreamNonBlocking));
+  const int slot = sc.graph_next;
+  sc.graph_next ^= 1;
+  if (!sc.graph_done[slot])
+    BM25_HIP(hipEventCreateWithFlags(&sc.graph_done[slot], hipEventDisableTiming));
   BM25_HIP(hipStreamBeginCapture(sc.cap_stream, hipStreamCaptureModeThreadLocal));
   const int rc = enqueue(sc.cap_stream);
   hipGraph_t g = nullptr;
@@ -285,37 +391,140 @@ static int launch_as_graph(SearchScratch& sc, hipStream_t s, const std::array<in
     if (rc != BM25_OK) return rc;
     return set_error(BM25_E_HIP, "graph capture failed: %s", hipGetErrorString(ec));
   }
+  hipGraphExec_t& ex = sc.graph_exec[slot];
+  if (ex) BM25_HIP(hipEventSynchronize(sc.graph_done[slot]));
   bool updated = false;
-  if (sc.graph_exec && sc.graph_cfg != cfg) {
-    (void)hipGraphExecDestroy(sc.graph_exec);
-    sc.graph_exec = nullptr;
+  if (ex && sc.graph_cfg[slot] != cfg) {
+    (void)hipGraphExecDestroy(ex);
+    ex = nullptr;
   }
-  if (sc.graph_exec) {
+  if (ex) {
     hipGraphNode_t bad = nullptr;
     hipGraphExecUpdateResult res = hipGraphExecUpdateError;
-    if (hipGraphExecUpdate(sc.graph_exec, g, &bad, &res) == hipSuccess &&
-        res == hipGraphExecUpdateSuccess) {
+    if (hipGraphExecUpdate(ex, g, &bad, &res) == hipSuccess && res == hipGraphExecUpdateSuccess) {
       updated = true;
       ++sc.graph_updates;
     } else {
       (void)hipGetLastError();  // a refused update is not an error of this call
-      (void)hipGraphExecDestroy(sc.graph_exec);
-      sc.graph_exec = nullptr;
+      (void)hipGraphExecDestroy(ex);
+      ex = nullptr;
     }
   }
   if (!updated) {
-    const hipError_t ei = hipGraphInstantiate(&sc.graph_exec, g, nullptr, nullptr, 0);
+    const hipError_t ei = hipGraphInstantiate(&ex, g, nullptr, nullptr, 0);
     if (ei != hipSuccess) {
-      sc.graph_exec = nullptr;
+      ex = nullptr;
       (void)hipGraphDestroy(g);
       return set_error(BM25_E_HIP, "graph instantiation failed: %s", hipGetErrorString(ei));
     }
     ++sc.graph_builds;
-    sc.graph_cfg = cfg;
+    sc.graph_cfg[slot] = cfg;
   }
   (void)hipGraphDestroy(g);
-  BM25_HIP(hipGraphLaunch(sc.graph_exec, s));
+  BM25_HIP(hipGraphLaunch(ex, s));
+  BM25_HIP(hipEventRecord(sc.graph_done[slot], s));
   return BM25_OK;
+}
+
+TileShape batch_shape(const bm25_index* idx, int32_t n, int32_t max_qlen, int32_t k_max) {
+  TileShape t;
+  if (idx->plan_fixed) {
+    t = idx->fixed_plan;
+  } else {
+    auto it = idx->tuned.find(shape_class(n, max_qlen, k_max));
+    t = (it != idx->tuned.end()) ? it->second : choose_shape(idx, n, max_qlen, k_max);
+  }
+  if (!shape_ok(t, k_max)) {
+    // a fixed or tuned plan made for smaller lists: keep its tile, shrink the query tile
+    t.q_tile = fit_q_tile(t.q_tile, kpl_for(k_max), t.waves,
+                          t.doc_tile / (64 * std::max(1, t.waves)));
+  }
+  return t;
+}
+
+// Tiling of a batch under shape t. Grouped order: the batch is permuted on the device so that
+// queries holding the same frequent (dense-row) tokens share query tiles; tiles are then q_tile
+// consecutive grouped queries, sized for the longest query. As given: tiles of up to q_tile
+// consecutive queries and kTileMaxPositions positions. Writes the tile bounds when tile_q0 is
+// not null (room for n + 1 tiles), else bounds n_tiles and ent from above.
+struct Tiling {
+  bool grouped = false;
+  int32_t n_tiles = 0;
+  int64_t ent = 0, ecap = 0, pcap = 0;
+};
+
+static Tiling tile_batch(const bm25_index* idx, const TileShape& t, const int64_t* q_off,
+                         int32_t n, int32_t max_qlen, int64_t positions, int32_t* tile_q0,
+                         int64_t* tile_e0) {
+  Tiling r;
+  const int W = t.waves, QT = t.q_tile;
+  const bool dense = !t.sparse_only && idx->n_dense > 0;
+  const int64_t grouped_pos = (int64_t)QT * max_qlen;
+  r.grouped = t.query_order != 2 && dense && n > QT && grouped_pos <= kTileMaxPositions;
+  if (r.grouped) {
+    int32_t i = 0;
+    for (int32_t q = 0; q < n; q += QT, ++i) {
+      if (tile_q0) {
+        tile_q0[i] = q;
+        tile_e0[i] = r.ent;
+      }
+      r.ent += grouped_pos + W;
+    }
+    r.n_tiles = i;
+    r.ecap = grouped_pos + W;
+    r.pcap = grouped_pos;
+  } else if (!tile_q0) {
+    r.n_tiles = n;
+    r.ent = positions + (int64_t)W * n;
+    r.ecap = std::min<int64_t>(positions, kTileMaxPositions) + W;
+    r.pcap = std::min<int64_t>(positions, kTileMaxPositions);
+  } else {
+    int32_t q = 0, i = 0;
+    while (q < n) {
+      tile_q0[i] = q;
+      tile_e0[i] = r.ent;
+      int64_t pos = 0;
+      int cnt = 0;
+      while (q < n && cnt < QT && pos + (q_off[q + 1] - q_off[q]) <= kTileMaxPositions) {
+        pos += q_off[q + 1] - q_off[q];
+        ++q;
+        ++cnt;
+      }
+      r.ent += pos + W;
+      r.ecap = std::max<int64_t>(r.ecap, pos + W);
+      r.pcap = std::max<int64_t>(r.pcap, pos);
+      ++i;
+    }
+    r.n_tiles = i;
+  }
+  if (tile_q0) {
+    tile_q0[r.n_tiles] = n;
+    tile_e0[r.n_tiles] = r.ent;
+  }
+  return r;
+}
+
+static ArenaNeed batch_need(const TileShape& t, const Tiling& tl, int32_t n, int64_t positions,
+                            int32_t k_max) {
+  ArenaNeed a;
+  a.n = n;
+  a.n_tiles = tl.n_tiles;
+  a.waves = t.waves;
+  a.ent = tl.ent;
+  a.positions = positions;
+  a.cand_keys = (int64_t)n * t.doc_groups * 64 * kpl_for(k_max);
+  a.ordered = tl.n_tiles > 1 && tl.n_tiles <= kOrderMax;
+  a.grouped = tl.grouped;
+  return a;
+}
+
+size_t batch_arena_bytes(const bm25_index* idx, int32_t n, int64_t positions, int32_t max_qlen,
+                         int32_t k_max) {
+  const TileShape t = batch_shape(idx, n, max_qlen, k_max);
+  const Tiling tl = tile_batch(idx, t, nullptr, n, max_qlen, positions, nullptr, nullptr);
+  ArenaNeed a = batch_need(t, tl, n, positions, k_max);
+  a.ordered = tl.n_tiles > 1;  // an upper bound: the as-given tiling may hold fewer tiles
+  return arena_layout(a).total;
 }
 
 int search_batch_impl(bm25_index* idx, const int32_t* q_ids, const int64_t* q_off, int32_t n,
@@ -325,94 +534,41 @@ int search_batch_impl(bm25_index* idx, const int32_t* q_ids, const int64_t* q_of
   BatchInfo info;
   int rc = check_batch(idx, q_ids, q_off, n, k, k_max, out_ids, out_scores, out_count, info);
   if (rc != BM25_OK || n == 0) return rc;
-  TileShape t;
-  if (force) {
-    t = *force;
-  } else if (idx->plan_fixed) {
-    t = idx->fixed_plan;
-  } else {
-    auto it = idx->tuned.find(shape_class(n, info.max_qlen, k_max));
-    t = (it != idx->tuned.end()) ? it->second : choose_shape(idx, n, info.max_qlen, k_max);
-  }
-  if (!force && !shape_ok(t, k_max)) {
-    // a fixed or tuned plan made for smaller lists: keep its tile, shrink the query tile
-    t.q_tile = fit_q_tile(t.q_tile, kpl_for(k_max), t.waves,
-                          t.doc_tile / (64 * std::max(1, t.waves)));
-  }
+  const TileShape t = force ? *force : batch_shape(idx, n, info.max_qlen, k_max);
   if (!shape_ok(t, k_max)) return set_error(BM25_E_INVAL, "invalid launch shape");
   const int W = t.waves, QT = t.q_tile, R = t.doc_tile / (64 * t.waves);
-  const int KPL = kpl_for(k_max), KP = 64 * KPL;
+  const int KPL = kpl_for(k_max);
 
   IndexView ix = index_view(idx, t.sparse_only != 0);
-  // Grouped order: the batch is permuted on the device so that queries holding the same
-  // frequent (dense-row) tokens share query tiles; tiles are then q_tile consecutive grouped
-  // queries, sized for the longest query. As given: tiles of up to q_tile consecutive queries
-  // and kTileMaxPositions positions.
-  const int64_t grouped_pos = (int64_t)QT * info.max_qlen;
-  const bool grouped = t.query_order != 2 && ix.dense_id != nullptr && n > QT &&
-                       grouped_pos <= kTileMaxPositions;
-  std::vector<int32_t> tile_q0;
-  std::vector<int64_t> tile_e0;
-  tile_q0.reserve(n / t.q_tile + 2);
-  tile_e0.reserve(n / t.q_tile + 2);
-  int64_t ent = 0, ecap = 0, pcap = 0;
-  if (grouped) {
-    for (int32_t q = 0; q < n; q += QT) {
-      tile_q0.push_back(q);
-      tile_e0.push_back(ent);
-      ent += grouped_pos + W;
-    }
-    ecap = grouped_pos + W;
-    pcap = grouped_pos;
-  } else {
-    int32_t q = 0;
-    while (q < n) {
-      tile_q0.push_back(q);
-      tile_e0.push_back(ent);
-      int64_t pos = 0;
-      int cnt = 0;
-      while (q < n && cnt < t.q_tile && pos + (q_off[q + 1] - q_off[q]) <= kTileMaxPositions) {
-        pos += q_off[q + 1] - q_off[q];
-        ++q;
-        ++cnt;
-      }
-      ent += pos + W;
-      ecap = std::max<int64_t>(ecap, pos + W);
-      pcap = std::max<int64_t>(pcap, pos);
-    }
-  }
-  const int32_t n_tiles = (int32_t)tile_q0.size();
-  tile_q0.push_back(n);
-  tile_e0.push_back(ent);
+  uint8_t* host = nullptr;
+  rc = acquire_staging(sc, n, &host);
+  if (rc != BM25_OK) return rc;
+  Staged hs;
+  stage_layout(host, n, hs);
+  stage_queries(hs, q_off, k, n, k_max);
+  const Tiling tl = tile_batch(idx, t, q_off, n, info.max_qlen, info.positions, hs.tile_q0,
+                               hs.tile_e0);
+  const bool grouped = tl.grouped;
+  const int32_t n_tiles = tl.n_tiles;
 
-  const int64_t lds = gather_lds(t, ecap, pcap);
+  const int64_t lds = gather_lds(t, tl.ecap, tl.pcap);
   if (lds > kMaxLdsBytes) return set_error(BM25_E_INVAL, "launch shape exceeds LDS");
   const int64_t G = t.doc_groups;
   const int64_t ntile_docs = std::max<int64_t>(1, (idx->n_docs + t.doc_tile - 1) / t.doc_tile);
   const int64_t group_docs = ((ntile_docs + G - 1) / G) * t.doc_tile;
-
-  BM25_RESERVE(sc.wave_e0, (size_t)n_tiles * (W + 1) * 4);
-  BM25_RESERVE(sc.qstat, (size_t)n * 4);
-  BM25_RESERVE(sc.entries, (size_t)std::max<int64_t>(ent, 1) * sizeof(Entry));
-  BM25_RESERVE(sc.members, (size_t)std::max<int64_t>(info.positions, 1) * 4);
-  BM25_RESERVE(sc.dense_ent, (size_t)std::max<int64_t>(info.positions, 1) * sizeof(DenseEntry));
-  BM25_RESERVE(sc.dense_n, (size_t)n_tiles * 4);
-  BM25_RESERVE(sc.cand, (size_t)n * G * KP * 8);
   // longest tiles first when there is more than one round of workgroups to balance
-  const bool ordered = n_tiles > 1 && n_tiles <= kOrderMax;
-  if (ordered) {
-    BM25_RESERVE(sc.tile_cost, (size_t)n_tiles * 4);
-    BM25_RESERVE(sc.order, (size_t)n_tiles * 4);
-  }
-  if (grouped) {
-    BM25_RESERVE(sc.perm, (size_t)n * 4);
-    BM25_RESERVE(sc.ids2, (size_t)std::max<int64_t>(info.positions, 1) * 4);
-    BM25_RESERVE(sc.off2, ((size_t)n + 1) * 8);
-    BM25_RESERVE(sc.k2, (size_t)n * 4);
-  }
+  const ArenaNeed need = batch_need(t, tl, n, info.positions, k_max);
+  const bool ordered = need.ordered;
+  const ArenaLayout L = arena_layout(need);
 
+  rc = scratch_begin(sc, s);
+  if (rc != BM25_OK) return rc;
+  uint8_t* base = nullptr;
+  rc = acquire_arena(sc, L.total, &base);
+  if (rc != BM25_OK) return rc;
   Staged dev;
-  rc = upload_plan(sc, s, n, n_tiles, q_off, k, k_max, tile_q0, tile_e0, dev);
+  stage_layout(base + L.meta, n, dev);
+  rc = upload_plan(sc, s, n, host, base + L.meta);
   if (rc != BM25_OK) return rc;
 
   if (grouped) {
@@ -426,7 +582,10 @@ int search_batch_impl(bm25_index* idx, const int32_t* q_ids, const int64_t* q_of
       reorder_lds.store(true, std::memory_order_release);
     }
   }
-  const bool graph = idx->use_graphs;
+  const bool graph = idx->use_graphs && !sc.no_alloc;
+  int32_t* const s_perm = reinterpret_cast<int32_t*>(base + L.perm);
+  uint64_t* const s_cand = reinterpret_cast<uint64_t*>(base + L.cand);
+  int32_t* const s_qstat = reinterpret_cast<int32_t*>(base + L.qstat);
   // Everything after the plan upload: grouping, planner, gather, merge. Enqueued on `q`, which
   // is the caller's stream, or the capture stream in graph mode.
   auto enqueue = [&](hipStream_t q) -> int {
@@ -442,10 +601,10 @@ int search_batch_impl(bm25_index* idx, const int32_t* q_ids, const int64_t* q_of
       ra.dense_rank = ix.dense_rank;
       ra.vocab = idx->vocab;
       ra.n = n;
-      ra.ids2 = sc.ids2.as<int32_t>();
-      ra.off2 = sc.off2.as<int64_t>();
-      ra.k2 = sc.k2.as<int32_t>();
-      ra.perm = sc.perm.as<int32_t>();
+      ra.ids2 = reinterpret_cast<int32_t*>(base + L.ids2);
+      ra.off2 = reinterpret_cast<int64_t*>(base + L.off2);
+      ra.k2 = reinterpret_cast<int32_t*>(base + L.k2);
+      ra.perm = s_perm;
       hipLaunchKernelGGL(k_reorder, dim3((unsigned)((n + kPlanSort - 1) / kPlanSort)),
                          dim3(kPlanThreads), kReorderLds, q, ra);
       BM25_HIP(hipGetLastError());
@@ -457,54 +616,55 @@ int search_batch_impl(bm25_index* idx, const int32_t* q_ids, const int64_t* q_of
     bv.q_ids = b_ids;
     bv.q_off = b_off;
     bv.q_k = b_k;
-    bv.q_stat = sc.qstat.as<int32_t>();
+    bv.q_stat = s_qstat;
     bv.tile_q0 = dev.tile_q0;
     bv.tile_e0 = dev.tile_e0;
-    bv.wave_e0 = sc.wave_e0.as<int32_t>();
-    bv.entries = sc.entries.as<Entry>();
-    bv.members = sc.members.as<int32_t>();
-    bv.dense_ent = sc.dense_ent.as<DenseEntry>();
-    bv.dense_n = sc.dense_n.as<int32_t>();
-    bv.tile_cost = ordered ? sc.tile_cost.as<float>() : nullptr;
+    bv.wave_e0 = reinterpret_cast<int32_t*>(base + L.wave_e0);
+    bv.entries = reinterpret_cast<Entry*>(base + L.entries);
+    bv.members = reinterpret_cast<int32_t*>(base + L.members);
+    bv.dense_ent = reinterpret_cast<DenseEntry*>(base + L.dense_ent);
+    bv.dense_n = reinterpret_cast<int32_t*>(base + L.dense_n);
+    bv.tile_cost = ordered ? reinterpret_cast<float*>(base + L.tile_cost) : nullptr;
     bv.n_queries = n;
     bv.n_tiles = n_tiles;
 
     hipLaunchKernelGGL(k_plan, dim3(n_tiles), dim3(kPlanThreads), 0, q, ix, bv, W);
     BM25_HIP(hipGetLastError());
+    int32_t* const order = ordered ? reinterpret_cast<int32_t*>(base + L.order) : nullptr;
     if (ordered) {
       hipLaunchKernelGGL(k_order, dim3(1), dim3(kPlanThreads), 0, q, bv.tile_cost, n_tiles,
-                         sc.order.as<int32_t>());
+                         order);
       BM25_HIP(hipGetLastError());
     }
 
     GatherArgs ga;
     ga.ix = ix;
     ga.bv = bv;
-    ga.order = ordered ? sc.order.as<int32_t>() : nullptr;
-    ga.cand = sc.cand.as<uint64_t>();
+    ga.order = order;
+    ga.cand = s_cand;
     ga.group_docs = group_docs;
     ga.n_groups = (int32_t)G;
-    ga.ecap = (int32_t)ecap;
-    ga.pcap = (int32_t)pcap;
+    ga.ecap = (int32_t)tl.ecap;
+    ga.pcap = (int32_t)tl.pcap;
     hipEvent_t tb = nullptr;
-    int r = graph ? BM25_OK : timed_begin(idx, q, &tb);
+    int r = (graph || sc.no_alloc) ? BM25_OK : timed_begin(idx, q, &tb);
     if (r != BM25_OK) return r;
     BM25_HIP(launch_gather(idx->params.store_dtype, W, QT, R, KPL,
                            dim3((unsigned)((int64_t)n_tiles * G)), (size_t)lds, q, ga));
-    r = graph ? BM25_OK : timed_end(idx, q, tb);
+    r = (graph || sc.no_alloc) ? BM25_OK : timed_end(idx, q, tb);
     if (r != BM25_OK) return r;
 
     MergeArgs ma;
-    ma.cand = sc.cand.as<uint64_t>();
+    ma.cand = s_cand;
     ma.q_ids = b_ids;
     ma.q_off = b_off;
     ma.q_k = b_k;
-    ma.q_stat = sc.qstat.as<int32_t>();
+    ma.q_stat = s_qstat;
     ma.theta32 = ix.theta32;
     ma.out_ids = out_ids;
     ma.out_scores = out_scores;
     ma.out_count = out_count;
-    ma.perm = grouped ? sc.perm.as<int32_t>() : nullptr;
+    ma.perm = grouped ? s_perm : nullptr;
     ma.n_docs = idx->n_docs;
     ma.lists = (int32_t)G;
     ma.k_max = k_max;
@@ -512,7 +672,11 @@ int search_batch_impl(bm25_index* idx, const int32_t* q_ids, const int64_t* q_of
     BM25_HIP(launch_merge(KPL, dim3(n), q, ma));
     return BM25_OK;
   };
-  if (!graph) return enqueue(s);
+  if (!graph) {
+    rc = enqueue(s);
+    if (rc != BM25_OK) return rc;
+    return scratch_end(sc, s);
+  }
   // graph mode: the timing events (if enabled) bracket the whole graph
   hipEvent_t tb = nullptr;
   rc = timed_begin(idx, s, &tb);
@@ -524,7 +688,9 @@ int search_batch_impl(bm25_index* idx, const int32_t* q_ids, const int64_t* q_of
                                         (int64_t)idx->params.store_dtype, (int64_t)grouped};
   rc = launch_as_graph(sc, s, cfg, enqueue);
   if (rc != BM25_OK) return rc;
-  return timed_end(idx, s, tb);
+  rc = timed_end(idx, s, tb);
+  if (rc != BM25_OK) return rc;
+  return scratch_end(sc, s);
 }
 
 int search_plain_impl(bm25_index* idx, const int32_t* q_ids, const int64_t* q_off, int32_t n,
@@ -550,46 +716,59 @@ int search_plain_impl(bm25_index* idx, const int32_t* q_ids, const int64_t* q_of
   const int64_t sweepers = (idx->n_docs + sweep_docs - 1) / sweep_docs;
   const int64_t G = (sweepers + W - 1) / W;
 
-  std::vector<int32_t> tile_q0(n + 1);
-  std::vector<int64_t> tile_e0(n + 1);
+  uint8_t* host = nullptr;
+  rc = acquire_staging(sc, n, &host);
+  if (rc != BM25_OK) return rc;
+  Staged hs;
+  stage_layout(host, n, hs);
+  stage_queries(hs, q_off, k, n, k_max);
   int64_t ent = 0;
   for (int32_t i = 0; i < n; ++i) {
-    tile_q0[i] = i;
-    tile_e0[i] = ent;
+    hs.tile_q0[i] = i;
+    hs.tile_e0[i] = ent;
     ent += (q_off[i + 1] - q_off[i]) + 1;
   }
-  tile_q0[n] = n;
-  tile_e0[n] = ent;
+  hs.tile_q0[n] = n;
+  hs.tile_e0[n] = ent;
 
-  BM25_RESERVE(sc.wave_e0, (size_t)n * 2 * 4);
-  BM25_RESERVE(sc.qstat, (size_t)n * 4);
-  BM25_RESERVE(sc.entries, (size_t)std::max<int64_t>(ent, 1) * sizeof(Entry));
-  BM25_RESERVE(sc.members, (size_t)std::max<int64_t>(info.positions, 1) * 4);
-  BM25_RESERVE(sc.dense_ent, (size_t)std::max<int64_t>(info.positions, 1) * sizeof(DenseEntry));
-  BM25_RESERVE(sc.dense_n, (size_t)n * 4);
   // candidate lists of up to kPlainMergeBatch queries (and at most kPlainCandBytes), merged by
   // one launch per batch
   const int64_t cand_per_query = G * KP * 8;
   const int32_t mb = (int32_t)std::max<int64_t>(
       1, std::min<int64_t>({(int64_t)n, (int64_t)kPlainMergeBatch, kPlainCandBytes / cand_per_query}));
-  BM25_RESERVE(sc.cand, (size_t)mb * G * KP * 8);
-  Staged dev;
-  rc = upload_plan(sc, s, n, n, q_off, k, k_max, tile_q0, tile_e0, dev);
+  ArenaNeed need;
+  need.n = n;
+  need.n_tiles = n;
+  need.waves = 1;
+  need.ent = ent;
+  need.positions = info.positions;
+  need.cand_keys = (int64_t)mb * G * KP;
+  const ArenaLayout L = arena_layout(need);
+  rc = scratch_begin(sc, s);
   if (rc != BM25_OK) return rc;
+  uint8_t* base = nullptr;
+  rc = acquire_arena(sc, L.total, &base);
+  if (rc != BM25_OK) return rc;
+  Staged dev;
+  stage_layout(base + L.meta, n, dev);
+  rc = upload_plan(sc, s, n, host, base + L.meta);
+  if (rc != BM25_OK) return rc;
+  uint64_t* const s_cand = reinterpret_cast<uint64_t*>(base + L.cand);
+  int32_t* const s_qstat = reinterpret_cast<int32_t*>(base + L.qstat);
 
   IndexView ix = index_view(idx, idx->plan_fixed && idx->fixed_plan.sparse_only != 0);
   BatchView bv;
   bv.q_ids = q_ids;
   bv.q_off = dev.q_off;
   bv.q_k = dev.q_k;
-  bv.q_stat = sc.qstat.as<int32_t>();
+  bv.q_stat = s_qstat;
   bv.tile_q0 = dev.tile_q0;
   bv.tile_e0 = dev.tile_e0;
-  bv.wave_e0 = sc.wave_e0.as<int32_t>();
-  bv.entries = sc.entries.as<Entry>();
-  bv.members = sc.members.as<int32_t>();
-  bv.dense_ent = sc.dense_ent.as<DenseEntry>();
-  bv.dense_n = sc.dense_n.as<int32_t>();
+  bv.wave_e0 = reinterpret_cast<int32_t*>(base + L.wave_e0);
+  bv.entries = reinterpret_cast<Entry*>(base + L.entries);
+  bv.members = reinterpret_cast<int32_t*>(base + L.members);
+  bv.dense_ent = reinterpret_cast<DenseEntry*>(base + L.dense_ent);
+  bv.dense_n = reinterpret_cast<int32_t*>(base + L.dense_n);
   bv.n_queries = n;
   bv.n_tiles = n;
   hipLaunchKernelGGL(k_plan, dim3(n), dim3(kPlanThreads), 0, s, ix, bv, 1);
@@ -598,18 +777,18 @@ int search_plain_impl(bm25_index* idx, const int32_t* q_ids, const int64_t* q_of
   SweepArgs sa;
   sa.ix = ix;
   sa.bv = bv;
-  sa.cand = sc.cand.as<uint64_t>();
+  sa.cand = s_cand;
   sa.sweep_docs = sweep_docs;
   sa.n_groups = (int32_t)G;
   sa.acc_bytes = (int32_t)acc_bytes;
   sa.ecap = (int32_t)ecap;
   sa.pcap = (int32_t)pcap;
   MergeArgs ma;
-  ma.cand = sc.cand.as<uint64_t>();
+  ma.cand = s_cand;
   ma.q_ids = q_ids;
   ma.q_off = dev.q_off;
   ma.q_k = dev.q_k;
-  ma.q_stat = sc.qstat.as<int32_t>();
+  ma.q_stat = s_qstat;
   ma.theta32 = ix.theta32;
   ma.out_ids = out_ids;
   ma.out_scores = out_scores;
@@ -622,7 +801,7 @@ int search_plain_impl(bm25_index* idx, const int32_t* q_ids, const int64_t* q_of
     const int32_t i1 = std::min<int32_t>(n, i0 + mb);
     for (int32_t i = i0; i < i1; ++i) {
       sa.query = i;
-      sa.cand = sc.cand.as<uint64_t>() + (size_t)(i - i0) * G * KP;
+      sa.cand = s_cand + (size_t)(i - i0) * G * KP;
       hipEvent_t tb;
       rc = timed_begin(idx, s, &tb);
       if (rc != BM25_OK) return rc;
@@ -634,7 +813,7 @@ int search_plain_impl(bm25_index* idx, const int32_t* q_ids, const int64_t* q_of
     ma.q_first = i0;
     BM25_HIP(launch_merge(KPL, dim3((unsigned)(i1 - i0)), s, ma));
   }
-  return BM25_OK;
+  return scratch_end(sc, s);
 }
 
 }  // namespace bm25
@@ -649,6 +828,7 @@ extern "C" int bm25_search_batch(const bm25_index* index, const int32_t* q_ids,
   if (!index) return set_error(BM25_E_INVAL, "index is NULL");
   bm25_index* idx = const_cast<bm25_index*>(index);
   std::lock_guard<std::mutex> g(idx->mu);
+  idx->alloc.stream = (hipStream_t)stream;
   return search_batch_impl(idx, q_ids, q_offsets, n_queries, k, k_max, out_ids, out_scores,
                            out_count, (hipStream_t)stream, idx->batch_scratch, nullptr);
 }
@@ -661,6 +841,7 @@ extern "C" int bm25_search_plain(const bm25_index* index, const int32_t* q_ids,
   if (!index) return set_error(BM25_E_INVAL, "index is NULL");
   bm25_index* idx = const_cast<bm25_index*>(index);
   std::lock_guard<std::mutex> g(idx->mu);
+  idx->alloc.stream = (hipStream_t)stream;
   return search_plain_impl(idx, q_ids, q_offsets, n_queries, k, k_max, out_ids, out_scores,
                            out_count, (hipStream_t)stream);
 }
@@ -692,13 +873,7 @@ extern "C" int bm25_search_get_plan(const bm25_index* index, int32_t n_queries,
   if (!index || !plan) return set_error(BM25_E_INVAL, "NULL argument");
   bm25_index* idx = const_cast<bm25_index*>(index);
   std::lock_guard<std::mutex> g(idx->mu);
-  TileShape t;
-  if (idx->plan_fixed) {
-    t = idx->fixed_plan;
-  } else {
-    auto it = idx->tuned.find(shape_class(n_queries, max_query_len, k_max));
-    t = (it != idx->tuned.end()) ? it->second : choose_shape(idx, n_queries, max_query_len, k_max);
-  }
+  const TileShape t = batch_shape(idx, n_queries, max_query_len, k_max);
   plan->q_tile = t.q_tile;
   plan->waves = t.waves;
   plan->doc_tile = t.doc_tile;
@@ -740,6 +915,7 @@ extern "C" int bm25_autotune(bm25_index* index, const int32_t* q_ids, const int6
   if (rc != BM25_OK) return rc;
   if (n_queries == 0) return set_error(BM25_E_INVAL, "autotune needs at least one query");
   hipStream_t s = (hipStream_t)stream;
+  index->alloc.stream = s;
   const TileShape base = choose_shape(index, n_queries, info.max_qlen, k_max);
   std::vector<TileShape> cands;
   const int kpl = kpl_for(k_max);

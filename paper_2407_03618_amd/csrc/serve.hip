@@ -33,21 +33,28 @@ struct Done {
   uint64_t ticket;
   int32_t k;
   int32_t count;
+  int64_t admit_ns;  // steady-clock time of admission into a micro-batch
   std::vector<int32_t> ids;
   std::vector<float> scores;
 };
 
+// One lane: a stream and its share of the budget, reserved at create as one device slab that
+// holds the micro-batch's query ids, result rows and search arena, plus pinned host staging.
 struct Lane {
   hipStream_t stream = nullptr;
   SearchScratch scratch;
-  DevBuf q_ids;
-  DevBuf out_ids, out_scores, out_count;
+  DevBuf slab;
+  int32_t* q_ids = nullptr;      // [pos_cap]
+  int32_t* out_ids = nullptr;    // [max_batch * max_k]
+  float* out_scores = nullptr;   // [max_batch * max_k]
+  int32_t* out_count = nullptr;  // [max_batch]
   PinnedBuf h_ids, h_out_ids, h_out_scores, h_out_count;
   std::vector<Request> batch;
   std::vector<int64_t> q_off;
   std::vector<int32_t> ks;
   int32_t k_max = 0;
-  int64_t bytes = 0;            // budget charged to this micro-batch
+  int64_t admit_ns = 0;
+  Clock::time_point busy_since{};
   bool busy = false;
   std::atomic<bool> finished{false};
 };
@@ -56,6 +63,11 @@ static int64_t kp_for(int k) {
   int64_t kp = 64;
   while (kp < k) kp *= 2;
   return kp;
+}
+
+static int64_t now_ns() {
+  return std::chrono::duration_cast<std::chrono::nanoseconds>(Clock::now().time_since_epoch())
+      .count();
 }
 
 }  // namespace bm25
@@ -72,20 +84,31 @@ struct bm25_server {
   std::thread sched;
   bool stop = false;
   int64_t in_flight = 0;   // admitted or waiting, not yet handed to done
-  int64_t budget_used = 0;
   uint64_t next_ticket = 1;
-  int64_t submitted = 0, completed = 0, batches = 0;
+  int64_t submitted = 0, completed = 0, batches = 0, rejected_busy = 0, rejected_nomem = 0;
   int32_t max_batch_seen = 0;
-  int64_t groups_est = 8;
-  std::string thread_error;
+  int32_t lanes_busy = 0, max_lanes_busy = 0;
+  double lane_busy_s = 0.0;
+  int64_t pos_cap = 0;     // query ids a lane holds
+  size_t arena_cap = 0;    // search arena bytes of a lane
 };
 
 namespace bm25 {
 
-// Device bytes a request charges to the budget: its share of the candidate lists, its result
-// rows, its ids, planner entries and members.
-static int64_t request_bytes(const bm25_server* sv, int64_t len, int32_t k) {
-  return sv->groups_est * kp_for(k) * 8 + (int64_t)k * 8 + 4 + len * (4 + 4 + 32) + 64;
+// Device bytes of a lane's slab outside the search arena: query ids, result rows, counts.
+static size_t lane_io_bytes(int64_t pos_cap, int32_t max_batch, int32_t max_k) {
+  auto up = [](size_t b) { return (b + 255) & ~(size_t)255; };
+  return up((size_t)pos_cap * 4) + 2 * up((size_t)max_batch * max_k * 4) +
+         up((size_t)max_batch * 4);
+}
+
+// Whether a micro-batch of n requests holding `positions` ids (the longest max_qlen) with lists
+// for k_max fits a lane.
+static bool fits_lane(const bm25_server* sv, int32_t n, int64_t positions, int32_t max_qlen,
+                      int32_t k_max) {
+  if (n > sv->cfg.max_batch || positions > sv->pos_cap) return false;
+  std::lock_guard<std::mutex> g(sv->idx->mu);  // the launch shape reads the index's plans
+  return batch_arena_bytes(sv->idx, n, positions, max_qlen, k_max) <= sv->arena_cap;
 }
 
 static void host_done(void* p) {
@@ -94,6 +117,7 @@ static void host_done(void* p) {
 }
 
 // Launches the lane's micro-batch. Called by the scheduler with the server lock released.
+// Every buffer was reserved at create; admission guaranteed that the batch fits them.
 static int launch_lane(bm25_server* sv, Lane& ln) {
   const int32_t n = (int32_t)ln.batch.size();
   ln.q_off.assign((size_t)n + 1, 0);
@@ -105,42 +129,39 @@ static int launch_lane(bm25_server* sv, Lane& ln) {
     ln.k_max = std::max(ln.k_max, ln.batch[i].k);
   }
   const int64_t P = ln.q_off[n];
-  auto grow = [](auto& buf, size_t bytes) -> int {
-    hipError_t e = buf.reserve(bytes);
-    return e == hipSuccess ? BM25_OK : set_error(BM25_E_NOMEM, "server allocation failed");
-  };
-  int rc;
-  if ((rc = grow(ln.q_ids, (size_t)std::max<int64_t>(P, 1) * 4))) return rc;
-  if ((rc = grow(ln.h_ids, (size_t)std::max<int64_t>(P, 1) * 4))) return rc;
+  if (P > sv->pos_cap || n > sv->cfg.max_batch || ln.k_max > sv->cfg.max_k)
+    return set_error(BM25_E_STATE, "micro-batch exceeds the lane's reserved capacity");
   const size_t rows = (size_t)n * ln.k_max;
-  if ((rc = grow(ln.out_ids, rows * 4))) return rc;
-  if ((rc = grow(ln.out_scores, rows * 4))) return rc;
-  if ((rc = grow(ln.out_count, (size_t)n * 4))) return rc;
-  if ((rc = grow(ln.h_out_ids, rows * 4))) return rc;
-  if ((rc = grow(ln.h_out_scores, rows * 4))) return rc;
-  if ((rc = grow(ln.h_out_count, (size_t)n * 4))) return rc;
   int32_t* hid = ln.h_ids.as<int32_t>();
   for (int32_t i = 0; i < n; ++i)
     if (!ln.batch[i].ids.empty())
       std::memcpy(hid + ln.q_off[i], ln.batch[i].ids.data(), ln.batch[i].ids.size() * 4);
   if (P > 0)
-    BM25_HIP(hipMemcpyAsync(ln.q_ids.ptr, hid, (size_t)P * 4, hipMemcpyHostToDevice, ln.stream));
+    BM25_HIP(hipMemcpyAsync(ln.q_ids, hid, (size_t)P * 4, hipMemcpyHostToDevice, ln.stream));
+  int rc;
   {
     std::lock_guard<std::mutex> g(sv->idx->mu);
-    rc = search_batch_impl(sv->idx, ln.q_ids.as<int32_t>(), ln.q_off.data(), n, ln.ks.data(),
-                           ln.k_max, ln.out_ids.as<int32_t>(), ln.out_scores.as<float>(),
-                           ln.out_count.as<int32_t>(), ln.stream, ln.scratch, nullptr);
+    rc = search_batch_impl(sv->idx, ln.q_ids, ln.q_off.data(), n, ln.ks.data(), ln.k_max,
+                           ln.out_ids, ln.out_scores, ln.out_count, ln.stream, ln.scratch,
+                           nullptr);
   }
   if (rc != BM25_OK) return rc;
-  BM25_HIP(hipMemcpyAsync(ln.h_out_ids.ptr, ln.out_ids.ptr, rows * 4, hipMemcpyDeviceToHost,
+  BM25_HIP(hipMemcpyAsync(ln.h_out_ids.ptr, ln.out_ids, rows * 4, hipMemcpyDeviceToHost,
                           ln.stream));
-  BM25_HIP(hipMemcpyAsync(ln.h_out_scores.ptr, ln.out_scores.ptr, rows * 4,
-                          hipMemcpyDeviceToHost, ln.stream));
-  BM25_HIP(hipMemcpyAsync(ln.h_out_count.ptr, ln.out_count.ptr, (size_t)n * 4,
+  BM25_HIP(hipMemcpyAsync(ln.h_out_scores.ptr, ln.out_scores, rows * 4, hipMemcpyDeviceToHost,
+                          ln.stream));
+  BM25_HIP(hipMemcpyAsync(ln.h_out_count.ptr, ln.out_count, (size_t)n * 4,
                           hipMemcpyDeviceToHost, ln.stream));
   ln.finished.store(false, std::memory_order_relaxed);
   BM25_HIP(hipLaunchHostFunc(ln.stream, host_done, &ln));
   return BM25_OK;
+}
+
+static void lane_idle(bm25_server* sv, Lane& ln) {
+  sv->lane_busy_s += std::chrono::duration<double>(Clock::now() - ln.busy_since).count();
+  sv->lanes_busy -= 1;
+  ln.batch.clear();
+  ln.busy = false;
 }
 
 // Moves a finished lane's results to the done queue. Server lock held.
@@ -154,16 +175,14 @@ static void reap_lane(bm25_server* sv, Lane& ln) {
     d.ticket = ln.batch[i].ticket;
     d.k = ln.batch[i].k;
     d.count = cnt[i];
+    d.admit_ns = ln.admit_ns;
     d.ids.assign(ids + (size_t)i * ln.k_max, ids + (size_t)i * ln.k_max + d.k);
     d.scores.assign(sc + (size_t)i * ln.k_max, sc + (size_t)i * ln.k_max + d.k);
     sv->done.push_back(std::move(d));
   }
   sv->completed += n;
   sv->in_flight -= n;
-  sv->budget_used -= ln.bytes;
-  ln.bytes = 0;
-  ln.batch.clear();
-  ln.busy = false;
+  lane_idle(sv, ln);
 }
 
 static void fail_lane(bm25_server* sv, Lane& ln, int code) {
@@ -172,16 +191,14 @@ static void fail_lane(bm25_server* sv, Lane& ln, int code) {
     d.ticket = r.ticket;
     d.k = r.k;
     d.count = code;
+    d.admit_ns = ln.admit_ns;
     d.ids.assign(r.k, -1);
     d.scores.assign(r.k, -INFINITY);
     sv->done.push_back(std::move(d));
   }
   sv->completed += (int64_t)ln.batch.size();
   sv->in_flight -= (int64_t)ln.batch.size();
-  sv->budget_used -= ln.bytes;
-  ln.bytes = 0;
-  ln.batch.clear();
-  ln.busy = false;
+  lane_idle(sv, ln);
 }
 
 static void scheduler(bm25_server* sv) {
@@ -207,11 +224,13 @@ static void scheduler(bm25_server* sv) {
         if (ln.busy || sv->waiting.empty()) continue;
         // one list-size class per micro-batch (the oldest request's), so that short lists do
         // not run with the list registers of the longest k; later requests of other classes
-        // keep their order for the next micro-batch
-        int64_t bytes = 0;
+        // keep their order for the next micro-batch. A request joins while the enlarged batch
+        // still fits the lane.
         const int64_t cls = kp_for(sv->waiting.front().k);
         const size_t window = (size_t)sv->cfg.max_batch * 4;
         size_t scanned = 0;
+        int64_t P = 0;
+        int32_t max_qlen = 0, k_max = 1;
         auto it = sv->waiting.begin();
         while (it != sv->waiting.end() && scanned < window &&
                (int32_t)ln.batch.size() < sv->cfg.max_batch) {
@@ -220,16 +239,22 @@ static void scheduler(bm25_server* sv) {
             ++it;
             continue;
           }
-          const int64_t b = request_bytes(sv, (int64_t)it->ids.size(), it->k);
-          if (sv->budget_used + bytes + b > sv->cfg.hbm_budget_bytes) break;
-          bytes += b;
+          const int64_t len = (int64_t)it->ids.size();
+          const int32_t ql = std::max<int32_t>(max_qlen, (int32_t)len);
+          const int32_t km = std::max<int32_t>(k_max, it->k);
+          if (!fits_lane(sv, (int32_t)ln.batch.size() + 1, P + len, ql, km)) break;
+          P += len;
+          max_qlen = ql;
+          k_max = km;
           ln.batch.push_back(std::move(*it));
           it = sv->waiting.erase(it);
         }
-        if (ln.batch.empty()) break;  // budget exhausted: wait for a lane to finish
+        if (ln.batch.empty()) break;  // cannot happen: a lone request always fits (submit)
         ln.busy = true;
-        ln.bytes = bytes;
-        sv->budget_used += bytes;
+        ln.admit_ns = now_ns();
+        ln.busy_since = Clock::now();
+        sv->lanes_busy += 1;
+        sv->max_lanes_busy = std::max(sv->max_lanes_busy, sv->lanes_busy);
         sv->batches += 1;
         sv->max_batch_seen = std::max<int32_t>(sv->max_batch_seen, (int32_t)ln.batch.size());
         lk.unlock();
@@ -268,16 +293,60 @@ extern "C" int bm25_serve_create(const bm25_index* index, const bm25_serve_confi
   if (c.max_batch < 1 || c.max_batch > 65536) return set_error(BM25_E_INVAL, "max_batch");
   if (c.max_k < 1 || c.max_k > BM25_MAX_K) return set_error(BM25_E_INVAL, "max_k");
   if (c.n_streams < 1 || c.n_streams > 8) return set_error(BM25_E_INVAL, "n_streams");
+  bm25_index* idx = const_cast<bm25_index*>(index);
   std::unique_ptr<bm25_server> sv(new bm25_server());
-  sv->idx = const_cast<bm25_index*>(index);
+  sv->idx = idx;
   sv->cfg = c;
-  {
-    const TileShape t = choose_shape(index, c.max_batch, 64, c.max_k);
-    sv->groups_est = t.doc_groups;
-  }
   BM25_HIP(hipSetDevice(index->device));
+  // each lane's share of the budget: query ids (room for every request at the mean length the
+  // share can plan, at least one longest query), result rows, and the rest as search arena
+  const int64_t share = c.hbm_budget_bytes / c.n_streams;
+  sv->pos_cap = std::max<int64_t>(BM25_MAX_QUERY_LEN, (int64_t)c.max_batch * 64);
+  const size_t io = lane_io_bytes(sv->pos_cap, c.max_batch, c.max_k);
+  if ((int64_t)io >= share)
+    return set_error(BM25_E_NOMEM, "a lane's share of the budget (%lld bytes) does not hold its "
+                     "result rows (%zu bytes)", (long long)share, io);
+  sv->arena_cap = (size_t)share - io;
+  if (!fits_lane(sv.get(), 1, BM25_MAX_QUERY_LEN, BM25_MAX_QUERY_LEN, c.max_k))
+    return set_error(BM25_E_NOMEM, "a lane's share of the budget (%lld bytes) does not hold one "
+                     "request of %d ids and k = %d", (long long)share, BM25_MAX_QUERY_LEN,
+                     c.max_k);
+  std::lock_guard<std::mutex> g(idx->mu);
+  idx->alloc.stream = nullptr;
   for (int i = 0; i < c.n_streams; ++i) {
     std::unique_ptr<Lane> ln(new Lane());
+    ln->slab.al = &idx->alloc;
+    hipError_t e = ln->slab.reserve((size_t)share);
+    if (e != hipSuccess)
+      return set_error(BM25_E_NOMEM, "reserving %lld bytes for lane %d failed: %s",
+                       (long long)share, i, hipGetErrorString(e));
+    uint8_t* p = ln->slab.as<uint8_t>();
+    auto take = [&](size_t bytes) {
+      uint8_t* r = p;
+      p += (bytes + 255) & ~(size_t)255;
+      return r;
+    };
+    const size_t rows = (size_t)c.max_batch * c.max_k;
+    ln->q_ids = reinterpret_cast<int32_t*>(take((size_t)sv->pos_cap * 4));
+    ln->out_ids = reinterpret_cast<int32_t*>(take(rows * 4));
+    ln->out_scores = reinterpret_cast<float*>(take(rows * 4));
+    ln->out_count = reinterpret_cast<int32_t*>(take((size_t)c.max_batch * 4));
+    ln->scratch.fixed = p;
+    ln->scratch.fixed_bytes = sv->arena_cap;
+    auto pin = [&](PinnedBuf& b, size_t bytes) -> int {
+      hipError_t pe = b.reserve(bytes);
+      return pe == hipSuccess ? BM25_OK
+                              : set_error(BM25_E_NOMEM, "pinned host allocation failed: %s",
+                                          hipGetErrorString(pe));
+    };
+    int rc;
+    if ((rc = pin(ln->h_ids, (size_t)sv->pos_cap * 4))) return rc;
+    if ((rc = pin(ln->h_out_ids, rows * 4))) return rc;
+    if ((rc = pin(ln->h_out_scores, rows * 4))) return rc;
+    if ((rc = pin(ln->h_out_count, (size_t)c.max_batch * 4))) return rc;
+    if ((rc = pin(ln->scratch.host, batch_staging_bytes(c.max_batch)))) return rc;
+    BM25_HIP(hipEventCreateWithFlags(&ln->scratch.host_free, hipEventDisableTiming));
+    BM25_HIP(hipEventCreateWithFlags(&ln->scratch.done, hipEventDisableTiming));
     BM25_HIP(hipStreamCreateWithFlags(&ln->stream, hipStreamNonBlocking));
     sv->lanes.push_back(std::move(ln));
   }
@@ -297,15 +366,21 @@ extern "C" int bm25_serve_submit(bm25_server* sv, const int32_t* q_ids, int32_t 
   for (int32_t i = 0; i < q_len; ++i)
     if (q_ids[i] < 0 || q_ids[i] >= V)
       return set_error(BM25_E_RANGE, "token id %d outside [0, %d)", q_ids[i], V);
-  if (request_bytes(sv, q_len, k) > sv->cfg.hbm_budget_bytes)
-    return set_error(BM25_E_NOMEM, "request needs more than the whole budget");
+  if (!fits_lane(sv, 1, q_len, q_len, k)) {
+    std::lock_guard<std::mutex> g(sv->mu);
+    sv->rejected_nomem += 1;
+    return set_error(BM25_E_NOMEM, "the request does not fit a lane's share of the budget");
+  }
   Request r;
   r.k = k;
   r.ids.assign(q_ids, q_ids + q_len);
   {
     std::lock_guard<std::mutex> g(sv->mu);
     if (sv->stop) return set_error(BM25_E_STATE, "server is stopping");
-    if (sv->in_flight >= sv->cfg.max_slots) return set_error(BM25_E_BUSY, "all slots in use");
+    if (sv->in_flight >= sv->cfg.max_slots) {
+      sv->rejected_busy += 1;
+      return set_error(BM25_E_BUSY, "all slots in use");
+    }
     r.ticket = sv->next_ticket++;
     *ticket = r.ticket;
     sv->waiting.push_back(std::move(r));
@@ -316,10 +391,12 @@ extern "C" int bm25_serve_submit(bm25_server* sv, const int32_t* q_ids, int32_t 
   return BM25_OK;
 }
 
-extern "C" int bm25_serve_poll(bm25_server* sv, uint64_t* tickets, int32_t* ids, float* scores,
-                               int32_t* counts, int32_t max_results, int32_t k_stride,
-                               int64_t timeout_us) {
-  clear_error();
+namespace bm25 {
+
+// bm25_serve_poll, also handing out each request's admission time when admit_ns is not null.
+static int poll_impl(bm25_server* sv, uint64_t* tickets, int32_t* ids, float* scores,
+                     int32_t* counts, int64_t* admit_ns, int32_t max_results, int32_t k_stride,
+                     int64_t timeout_us) {
   if (!sv || !tickets || !counts || max_results < 1 || k_stride < 1)
     return set_error(BM25_E_INVAL, "bad poll arguments");
   std::unique_lock<std::mutex> lk(sv->mu);
@@ -336,6 +413,7 @@ extern "C" int bm25_serve_poll(bm25_server* sv, uint64_t* tickets, int32_t* ids,
     }
     tickets[r] = d.ticket;
     counts[r] = d.count;
+    if (admit_ns) admit_ns[r] = d.admit_ns;
     if (ids) {
       int32_t* row = ids + (size_t)r * k_stride;
       std::copy(d.ids.begin(), d.ids.end(), row);
@@ -352,16 +430,35 @@ extern "C" int bm25_serve_poll(bm25_server* sv, uint64_t* tickets, int32_t* ids,
   return r;
 }
 
-extern "C" int bm25_serve_stats(bm25_server* sv, int64_t* submitted, int64_t* completed,
-                                int64_t* batches, int32_t* max_batch_seen, int32_t* waiting) {
+}  // namespace bm25
+
+extern "C" int bm25_serve_poll(bm25_server* sv, uint64_t* tickets, int32_t* ids, float* scores,
+                               int32_t* counts, int32_t max_results, int32_t k_stride,
+                               int64_t timeout_us) {
   clear_error();
-  if (!sv) return set_error(BM25_E_INVAL, "server is NULL");
+  return poll_impl(sv, tickets, ids, scores, counts, nullptr, max_results, k_stride, timeout_us);
+}
+
+extern "C" int bm25_serve_stats(bm25_server* sv, bm25_serve_counters* out) {
+  clear_error();
+  if (!sv || !out) return set_error(BM25_E_INVAL, "NULL argument");
   std::lock_guard<std::mutex> g(sv->mu);
-  if (submitted) *submitted = sv->submitted;
-  if (completed) *completed = sv->completed;
-  if (batches) *batches = sv->batches;
-  if (max_batch_seen) *max_batch_seen = sv->max_batch_seen;
-  if (waiting) *waiting = (int32_t)sv->waiting.size();
+  bm25_serve_counters c{};
+  c.submitted = sv->submitted;
+  c.completed = sv->completed;
+  c.batches = sv->batches;
+  c.rejected_busy = sv->rejected_busy;
+  c.rejected_nomem = sv->rejected_nomem;
+  c.max_batch_seen = sv->max_batch_seen;
+  c.waiting = (int32_t)sv->waiting.size();
+  c.lanes_busy = sv->lanes_busy;
+  c.max_lanes_busy = sv->max_lanes_busy;
+  double busy = sv->lane_busy_s;
+  const auto now = Clock::now();
+  for (auto& lp : sv->lanes)
+    if (lp->busy) busy += std::chrono::duration<double>(now - lp->busy_since).count();
+  c.lane_busy_s = busy;
+  *out = c;
   return BM25_OK;
 }
 
@@ -379,9 +476,14 @@ extern "C" int bm25_serve_destroy(bm25_server* sv) {
   for (auto& lp : sv->lanes) {
     if (lp->stream) {
       (void)hipStreamSynchronize(lp->stream);
-      lp->scratch.release_handles();
       (void)hipStreamDestroy(lp->stream);
     }
+    lp->scratch.release_handles();
+  }
+  {
+    std::lock_guard<std::mutex> g(sv->idx->mu);
+    sv->idx->alloc.stream = nullptr;
+    sv->lanes.clear();  // slabs go back to the index's allocator
   }
   delete sv;
   return BM25_OK;
@@ -394,8 +496,8 @@ extern "C" int bm25_serve_destroy(bm25_server* sv) {
 // admitted; their wait counts in their latency.
 extern "C" int bm25_serve_replay(bm25_server* sv, const int32_t* q_ids, const int64_t* q_offsets,
                                  const int32_t* k, const double* arrival_us, int32_t n,
-                                 double* lat_us, int32_t* out_ids, float* out_scores,
-                                 int32_t* out_count, int32_t k_stride) {
+                                 double* lat_us, double* queue_us, int32_t* out_ids,
+                                 float* out_scores, int32_t* out_count, int32_t k_stride) {
   clear_error();
   if (!sv || !q_offsets || !k || !arrival_us || !lat_us || n < 0 || k_stride < 1)
     return set_error(BM25_E_INVAL, "bad replay arguments");
@@ -429,10 +531,14 @@ extern "C" int bm25_serve_replay(bm25_server* sv, const int32_t* q_ids, const in
   std::vector<uint64_t> tb(256);
   std::vector<int32_t> cb(256), ib((size_t)256 * k_stride);
   std::vector<float> sb((size_t)256 * k_stride);
+  std::vector<int64_t> ab(256);
+  const int64_t t0_ns = std::chrono::duration_cast<std::chrono::nanoseconds>(
+                            t0.time_since_epoch()).count();
   uint64_t first_ticket = 0;
   while (got < n) {
-    const int r = bm25_serve_poll(sv, tb.data(), ib.data(), sb.data(), cb.data(), 256, k_stride,
-                                  2000);
+    const int r = poll_impl(sv, tb.data(), out_ids ? ib.data() : nullptr,
+                            out_scores ? sb.data() : nullptr, cb.data(), ab.data(), 256, k_stride,
+                            2000);
     const auto now = Clock::now();
     if (r == BM25_E_TIMEOUT) {
       if (submit_rc.load() != BM25_OK) break;
@@ -453,6 +559,7 @@ extern "C" int bm25_serve_replay(bm25_server* sv, const int32_t* q_ids, const in
       const double done_us =
           std::chrono::duration<double, std::micro>(now - t0).count();
       lat_us[i] = done_us - arrival_us[i];
+      if (queue_us) queue_us[i] = (double)(ab[j] - t0_ns) / 1000.0 - arrival_us[i];
       if (out_count) out_count[i] = cb[j];
       if (out_ids)
         std::copy(ib.begin() + (size_t)j * k_stride, ib.begin() + (size_t)(j + 1) * k_stride,

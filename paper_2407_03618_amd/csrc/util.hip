@@ -9,19 +9,18 @@
 
 namespace bm25 {
 
-static thread_local std::string g_last_error;
+// Fixed-size per-thread message buffer: reporting an error allocates nothing.
+static thread_local char g_last_error[512];
 
 int set_error(int code, const char* fmt, ...) {
-  char buf[512];
   va_list ap;
   va_start(ap, fmt);
-  vsnprintf(buf, sizeof(buf), fmt, ap);
+  vsnprintf(g_last_error, sizeof(g_last_error), fmt, ap);
   va_end(ap);
-  g_last_error = buf;
   return code;
 }
 
-void clear_error() { g_last_error.clear(); }
+void clear_error() { g_last_error[0] = '\0'; }
 
 // Plain streaming copy, 16 bytes per lane per step; the tail (n % 16) is copied bytewise.
 __global__ __launch_bounds__(256) void k_copy(const uint4* __restrict__ src, uint4* __restrict__ dst,
@@ -37,7 +36,7 @@ __global__ __launch_bounds__(256) void k_copy(const uint4* __restrict__ src, uin
 
 using namespace bm25;
 
-extern "C" const char* bm25_last_error(void) { return g_last_error.c_str(); }
+extern "C" const char* bm25_last_error(void) { return g_last_error; }
 
 extern "C" int bm25_copy_bytes(void* dst, const void* src, int64_t n_bytes, void* stream) {
   clear_error();

@@ -34,7 +34,10 @@ def oracle_scores(ref: eager.EagerIndex, query):
     return b, absS
 
 
-def check_query(ids, scores, count, b, absS, k, rtol, where=""):
+def check_query(ids, scores, count, b, absS, k, rtol, where="", all_errors=False):
+    """Checks one query's returned rows against the oracle (see the module docstring); returns
+    the largest relative error, or with all_errors the relative error of every returned
+    document."""
     n = b.shape[0]
     kk = min(int(k), n)
     assert int(count) == kk, f"{where}: count {count} != {kk}"
@@ -59,7 +62,10 @@ def check_query(ids, scores, count, b, absS, k, rtol, where=""):
     assert np.all(np.diff(top_sc) <= 0), f"{where}: scores not descending"
     eq = np.flatnonzero(np.diff(top_sc) == 0)
     assert np.all(top_ids[eq] < top_ids[eq + 1]), f"{where}: equal scores not in id order"
-    return float((err / np.maximum(absS[top_ids], 1e-30)).max(initial=0.0))
+    rel = err / np.maximum(absS[top_ids], 1e-30)
+    if all_errors:
+        return rel
+    return float(rel.max(initial=0.0))
 
 
 def check_batch(ref, q_ids, q_offsets, ks, ids, scores, counts, rtol, where="", sample=None):

@@ -58,7 +58,8 @@ def _alone_and_in_mix(c, q, idx, ref):
     mix = _collect(srv, q.n, 1000)
     st = srv.stats()
     assert st["batches"] >= q.n + 2, st  # the mix ran as several micro-batches
-    assert st["max_batch"] > 1, st
+    assert st["max_batch_seen"] > 1, st
+    assert st["completed"] == 2 * q.n and st["rejected_busy"] == 0, st
     for i, t in enumerate(tickets):
         k = int(q.k[i])
         cnt_a, ids_a, sc_a = alone[i]
@@ -87,11 +88,10 @@ def test_admission_errors(setup):
         srv.submit([1, 2], 101)
     assert e.value.code == -1
     srv.close()
-    tiny = Server(idx, hbm_budget_bytes=1000, max_slots=8, max_batch=4, max_k=100, n_streams=1)
+    # a budget that cannot hold one request of the longest query is refused at create
     with pytest.raises(BM25Error) as e:
-        tiny.submit([1, 2], 100)
+        Server(idx, hbm_budget_bytes=1000, max_slots=8, max_batch=4, max_k=100, n_streams=1)
     assert e.value.code == -3
-    tiny.close()
 
 
 def test_replay_open_loop(setup):
@@ -100,9 +100,37 @@ def test_replay_open_loop(setup):
     srv = Server(idx, hbm_budget_bytes=1 << 30, max_slots=4096, max_batch=32, max_k=1000,
                  n_streams=2)
     arrivals = np.cumsum(np.full(q.n, 200.0))  # 5k requests/s
-    lat, ids, sc, cnt = srv.replay(q.q_ids, q.q_offsets, q.k, arrivals, 1000)
+    lat, queue, ids, sc, cnt = srv.replay(q.q_ids, q.q_offsets, q.k, arrivals, 1000)
     assert np.all(np.isfinite(lat)) and np.all(lat > 0)
+    assert np.all(np.isfinite(queue)) and np.all(queue >= 0) and np.all(queue <= lat)
     for i in range(q.n):
         b, absS = oracle_scores(ref, q.query(i))
         check_query(ids[i], sc[i], cnt[i], b, absS, int(q.k[i]), RTOL["f16"], f"replay {i}")
     srv.close()
+
+
+def test_budget_reserved_at_create_and_held(setup):
+    """The server takes its whole budget from the index's allocator (PyTorch's caching
+    allocator) at create; a run of mixed k and lengths allocates nothing more, and close returns
+    it."""
+    import torch
+    from paper_2407_03618_amd import Server
+    c, q, idx, ref = setup
+    torch.cuda.synchronize()
+    before = torch.cuda.memory_allocated()
+    idx_before = idx.device_bytes()
+    budget = 256 << 20
+    srv = Server(idx, hbm_budget_bytes=budget, max_slots=4096, max_batch=64, max_k=1000,
+                 n_streams=2)
+    held = torch.cuda.memory_allocated() - before
+    assert budget - 1024 <= held <= budget + 4096, held
+    arrivals = np.cumsum(np.full(q.n, 50.0))
+    lat, queue, _, _, cnt = srv.replay(q.q_ids, q.q_offsets, q.k, arrivals, 1000,
+                                       keep_results=False)
+    assert np.all(cnt == np.minimum(q.k, c.n_docs))
+    assert torch.cuda.memory_allocated() - before == held
+    assert idx.device_bytes() == idx_before  # lanes do not grow the index's scratch
+    st = srv.stats()
+    assert st["completed"] == q.n and st["max_lanes_busy"] >= 1 and st["lane_busy_s"] > 0, st
+    srv.close()
+    assert torch.cuda.memory_allocated() == before

@@ -150,6 +150,26 @@ def test_topk_against_argpartition():
             assert set(np.flatnonzero(s > kth)) <= set(ids)
 
 
+def test_partitioned_search_agrees_with_the_full_order():
+    """The paper's partition-then-sort top-k returns the scores of the definitional full sort;
+    ids differ only among ties at the k-th score."""
+    for seed in range(20):
+        c = make_tiny_corpus(seed)
+        if int(np.diff(c.doc_offsets).sum()) == 0:
+            continue
+        idx = eager.build_index(c.tokens, c.doc_offsets, c.vocab)
+        qb = make_tiny_queries(seed, c.vocab, n=8)
+        for i in range(qb.n):
+            q = qb.query(i)
+            b = eager.scores(idx, q)
+            for k in (1, 3, c.n_docs, c.n_docs + 2):
+                ids_a, s_a = eager.search(idx, q, k)
+                ids_b, s_b = eager.search_partitioned(idx, q, k)
+                np.testing.assert_array_equal(s_a, s_b)
+                assert set(np.flatnonzero(b > s_a[-1])) <= set(ids_b.tolist())
+                assert len(set(ids_b.tolist())) == len(ids_b)
+
+
 def test_lucene_idf_closed_form_and_monotone():
     # ln((N - DF + 0.5)/(DF + 0.5) + 1) = ln((N + 1)/(DF + 0.5))
     for n in (1, 2, 3, 10, 1000, 8_800_000):
