@@ -346,6 +346,69 @@ int bm25_serve_replay(bm25_server* server, const int32_t* q_ids, const int64_t* 
 int bm25_serve_destroy(bm25_server* server);
 
 /* ---------------------------------------------------------------------------------------------
+ * Tokenization and vocabulary mapping (Section 2, "Tokenization"): the step in front of the index
+ * build, for callers that hold text rather than token ids.
+ *
+ * A document is UTF-8 text. Its words are the matches of the pattern (?u)\b\w\w+\b: maximal runs
+ * of at least two word characters, where a word character is one that Python's \w matches
+ * (str.isalnum() or "_"), over the whole code space of the Unicode version the library was built
+ * with. Bytes that do not form valid UTF-8 (stray continuation bytes, invalid or truncated
+ * sequences, overlong forms, surrogates, code points above U+10FFFF) separate words. With
+ * BM25_TOK_LOWERCASE each code point first takes its lowercase form as Python's str.lower()
+ * gives it (U+0130 becomes "i" followed by U+0307, which ends the word). A dictionary maps each
+ * distinct word to an id, in order of first occurrence in the corpus (documents in order, words in
+ * order inside a document). Stemming and stopword removal are not applied.
+ */
+typedef struct bm25_vocab bm25_vocab;  /* opaque: the dictionary and the tokenized corpus */
+#define BM25_TOK_LOWERCASE 1
+
+/* Tokenizes a corpus and builds its dictionary. Synchronous.
+ * text        device uint8[n_bytes], the documents back to back (n_bytes < 2^32 - 1)
+ * doc_offsets device int64[n_docs + 1]: document d is text[doc_offsets[d] .. doc_offsets[d+1]);
+ *             doc_offsets[0] = 0, non-decreasing, doc_offsets[n_docs] = n_bytes
+ * flags       0 or BM25_TOK_LOWERCASE
+ * allocator   device memory provider (NULL: hipMalloc), as for bm25_index_build
+ * out         receives the vocabulary; *n_tokens and *vocab_size (either may be NULL) receive
+ *             the corpus's word count and the number of distinct words.
+ * Errors: BM25_E_INVAL for NULL pointers, sizes out of range or unknown flags; BM25_E_RANGE for
+ * malformed offsets; BM25_E_STATE if two distinct words share a 64-bit hash (detected by comparing
+ * every word with its dictionary entry; nothing is built); BM25_E_NOMEM, BM25_E_HIP. */
+int bm25_tokenize_corpus(const uint8_t* text, int64_t n_bytes, const int64_t* doc_offsets,
+                         int64_t n_docs, int32_t flags, const bm25_allocator* allocator,
+                         void* stream, bm25_vocab** out, int64_t* n_tokens, int32_t* vocab_size);
+
+/* Sizes of a vocabulary: documents, corpus words, distinct words, bytes of the words' UTF-8 and
+ * the flags it was built with. Any pointer may be NULL. */
+int bm25_vocab_info(const bm25_vocab* vocab, int64_t* n_docs, int64_t* n_tokens,
+                    int32_t* vocab_size, int64_t* word_bytes, int32_t* flags);
+
+/* Copies the tokenized corpus, ready for bm25_index_build with vocab_size as V: token_ids
+ * (device int32[n_tokens]) and doc_token_offsets (device int64[n_docs + 1]). Stream-ordered;
+ * either pointer may be NULL. */
+int bm25_vocab_corpus(const bm25_vocab* vocab, int32_t* token_ids, int64_t* doc_token_offsets,
+                      void* stream);
+
+/* Copies the words: word_offsets (device uint32[vocab_size + 1]) and word_bytes (device
+ * uint8[word_bytes]): word i is word_bytes[word_offsets[i] .. word_offsets[i+1]) in UTF-8, after
+ * lowercasing when the vocabulary was built with it. Stream-ordered; either pointer may be NULL. */
+int bm25_vocab_words(const bm25_vocab* vocab, uint32_t* word_offsets, uint8_t* word_bytes,
+                     void* stream);
+
+/* Maps texts (queries) to ids of the vocabulary with the same splitting and case rule; words not
+ * in the vocabulary are dropped. Synchronous.
+ * text, offsets  as for bm25_tokenize_corpus (n_texts texts)
+ * ids            device int32[ids_capacity]: the ids, text after text
+ * id_offsets     device int64[n_texts + 1]: text i holds ids[id_offsets[i] .. id_offsets[i+1])
+ * n_ids          host: receives the number of ids, also when ids is too small, in which case
+ *                BM25_E_RANGE is returned and nothing is written to ids. */
+int bm25_vocab_map(const bm25_vocab* vocab, const uint8_t* text, int64_t n_bytes,
+                   const int64_t* offsets, int64_t n_texts, int32_t* ids, int64_t ids_capacity,
+                   int64_t* id_offsets, int64_t* n_ids, void* stream);
+
+/* Frees the vocabulary. NULL is a no-op. */
+void bm25_vocab_free(bm25_vocab* vocab);
+
+/* ---------------------------------------------------------------------------------------------
  * Utilities. */
 
 /* Plain device-to-device copy kernel of n bytes (both pointers 16-byte aligned), stream-ordered.

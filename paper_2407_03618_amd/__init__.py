@@ -5,5 +5,5 @@ The hot path lives in hand-written HIP kernels compiled into ``libbm25_mi355x.so
 ``python -m paper_2407_03618_amd.build``.
 """
 from .bm25 import (  # noqa: F401
-    BM25Error, Index, Server, copy_bytes, load_library, LIB_PATH, VARIANTS, DTYPES, EXPORTED,
+    BM25Error, Index, Server, Vocab, copy_bytes, load_library, LIB_PATH, VARIANTS, DTYPES, EXPORTED,
 )

@@ -36,7 +36,10 @@ EXPORTED = (
     "bm25_autotune", "bm25_kernel_timing", "bm25_kernel_time_read",
     "bm25_serve_create", "bm25_serve_submit", "bm25_serve_poll", "bm25_serve_stats",
     "bm25_serve_replay", "bm25_serve_destroy", "bm25_copy_bytes", "bm25_last_error",
+    "bm25_tokenize_corpus", "bm25_vocab_info", "bm25_vocab_corpus", "bm25_vocab_words",
+    "bm25_vocab_map", "bm25_vocab_free",
 )
+TOK_LOWERCASE = 1
 
 
 class Params(ctypes.Structure):
@@ -149,6 +152,14 @@ def load_library() -> ctypes.CDLL:
     L.bm25_copy_bytes.argtypes = [vp, vp, i64, vp]
     L.bm25_last_error.argtypes = []
     L.bm25_last_error.restype = ctypes.c_char_p
+    L.bm25_tokenize_corpus.argtypes = [vp, i64, vp, i64, i32, P(Allocator), vp, P(vp), P(i64),
+                                       P(i32)]
+    L.bm25_vocab_info.argtypes = [vp, P(i64), P(i64), P(i32), P(i64), P(i32)]
+    L.bm25_vocab_corpus.argtypes = [vp, vp, vp, vp]
+    L.bm25_vocab_words.argtypes = [vp, vp, vp, vp]
+    L.bm25_vocab_map.argtypes = [vp, vp, i64, vp, i64, vp, i64, vp, P(i64), vp]
+    L.bm25_vocab_free.argtypes = [vp]
+    L.bm25_vocab_free.restype = None
     _lib = L
     return L
 
@@ -453,3 +464,81 @@ class Server:
         except Exception:
             pass
 
+
+class Vocab:
+    """Tokenized corpus and its word dictionary, built by the library's kernels from device
+    UTF-8 text (Section 2, "Tokenization")."""
+
+    def __init__(self, text, doc_offsets, lowercase: bool = False, stream=None,
+                 allocator: str = "torch"):
+        torch = _torch()
+        L = load_library()
+        if not (text.is_cuda and doc_offsets.is_cuda):
+            raise ValueError("text and doc_offsets must be device tensors")
+        if text.dtype != torch.uint8 or doc_offsets.dtype != torch.int64:
+            raise ValueError("text must be uint8 and doc_offsets int64")
+        text = text.contiguous()
+        doc_offsets = doc_offsets.contiguous()
+        self._allocator = TorchAllocator(text.device.index) if allocator else None
+        h = ctypes.c_void_p()
+        nt = ctypes.c_int64()
+        nv = ctypes.c_int32()
+        _check(L.bm25_tokenize_corpus(
+            _ptr(text), text.numel(), _ptr(doc_offsets), doc_offsets.numel() - 1,
+            TOK_LOWERCASE if lowercase else 0,
+            ctypes.byref(self._allocator.struct) if self._allocator else None,
+            _stream_ptr(stream), ctypes.byref(h), ctypes.byref(nt), ctypes.byref(nv)))
+        self._h = h
+        self.n_docs = doc_offsets.numel() - 1
+        self.n_tokens = nt.value
+        self.vocab_size = nv.value
+        self.lowercase = bool(lowercase)
+
+    def corpus(self, stream=None):
+        """(token_ids int32[n_tokens], doc_offsets int64[n_docs + 1]) on the device."""
+        torch = _torch()
+        ids = torch.empty(max(self.n_tokens, 1), dtype=torch.int32, device="cuda")
+        off = torch.empty(self.n_docs + 1, dtype=torch.int64, device="cuda")
+        _check(load_library().bm25_vocab_corpus(self._h, _ptr(ids), _ptr(off),
+                                                _stream_ptr(stream)))
+        return ids[:self.n_tokens], off
+
+    def words(self, stream=None) -> list:
+        """The words by id (host strings)."""
+        torch = _torch()
+        nb = ctypes.c_int64()
+        _check(load_library().bm25_vocab_info(self._h, None, None, None, ctypes.byref(nb), None))
+        off = torch.empty(self.vocab_size + 1, dtype=torch.int32, device="cuda")
+        data = torch.empty(max(nb.value, 1), dtype=torch.uint8, device="cuda")
+        _check(load_library().bm25_vocab_words(self._h, _ptr(off), _ptr(data),
+                                               _stream_ptr(stream)))
+        torch.cuda.synchronize()
+        o = off.cpu().numpy().view(np.uint32).astype(np.int64)
+        b = data.cpu().numpy().tobytes()
+        return [b[o[i]:o[i + 1]].decode("utf-8") for i in range(self.vocab_size)]
+
+    def map(self, text, offsets, stream=None):
+        """Ids of the texts' words (device int32) and per-text offsets (device int64[n+1])."""
+        torch = _torch()
+        L = load_library()
+        n = offsets.numel() - 1
+        id_off = torch.empty(n + 1, dtype=torch.int64, device="cuda")
+        cnt = ctypes.c_int64()
+        cap = max(1, text.numel() // 2 + 1)  # a word takes at least two bytes
+        ids = torch.empty(cap, dtype=torch.int32, device="cuda")
+        _check(L.bm25_vocab_map(self._h, _ptr(text), text.numel(), _ptr(offsets), n, _ptr(ids),
+                                cap, _ptr(id_off), ctypes.byref(cnt), _stream_ptr(stream)))
+        return ids[:cnt.value], id_off
+
+    def free(self) -> None:
+        if getattr(self, "_h", None):
+            load_library().bm25_vocab_free(self._h)
+            self._h = None
+
+    def __del__(self):
+        if sys.is_finalizing():
+            return
+        try:
+            self.free()
+        except Exception:
+            pass

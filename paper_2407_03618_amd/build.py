@@ -34,6 +34,7 @@ COMMON = [
 ]
 
 UNITS = [
+    ("tokenize.hip", []),
     ("index_build.hip", []),
     ("search.hip", []),
     ("util.hip", []),
@@ -59,6 +60,12 @@ def _compile(unit, extra, verbose):
 
 def build(verbose: bool = False, jobs: int | None = None) -> str:
     os.makedirs(BUILD_DIR, exist_ok=True)
+    # Unicode tables of the tokenizer, generated from this Python's character database
+    gen = os.path.join(CSRC, "gen_unicode_tables.py")
+    r = subprocess.run([sys.executable, gen, os.path.join(BUILD_DIR, "unicode_tables.inc")],
+                       capture_output=True, text=True)
+    if r.returncode != 0:
+        raise RuntimeError(f"unicode table generation failed:\n{r.stdout}\n{r.stderr}")
     jobs = jobs or max(1, min(len(UNITS), os.cpu_count() or 1))
     with ThreadPoolExecutor(jobs) as ex:
         objs = list(ex.map(lambda u: _compile(u[0], u[1], verbose), UNITS))
