@@ -195,6 +195,26 @@ int bm25_search_plain(const bm25_index* index, const int32_t* q_ids, const int64
                       int32_t n_queries, const int32_t* k, int32_t k_max, int32_t* out_ids,
                       float* out_scores, int32_t* out_count, void* stream);
 
+/* bm25_search_batch without any allocation, for callers that cannot allocate: code under HIP
+ * graph capture, tight serving loops, harnesses that forbid allocation. Same arguments, results
+ * and errors as bm25_search_batch (eager launches only: graph mode and kernel timing do not
+ * apply). Its scratch is a fixed device array of BM25_NOALLOC_SCRATCH_BYTES bytes inside the
+ * library (one per device, held until the process ends) and its host plan a fixed host array of
+ * room for BM25_NOALLOC_MAX_QUERIES queries; nothing is allocated through hipMalloc, the index's
+ * allocator or the host heap. A batch whose scratch does not fit (more queries, longer queries
+ * or larger k than the array holds; about 4096 queries of 30 ids at k = 100 fit) or that holds
+ * more than BM25_NOALLOC_MAX_QUERIES queries is refused with BM25_E_NOMEM before any device
+ * work. The index must live on the current device (else BM25_E_INVAL). Every call on one device
+ * shares that device's arrays and leaves its contents behind: calls that overlap on one device
+ * (several threads, or several streams whose work overlaps) race, so the caller serialises them
+ * (stream order on one stream does). */
+#define BM25_NOALLOC_SCRATCH_BYTES (64 << 20)
+#define BM25_NOALLOC_MAX_QUERIES 65536
+int bm25_search_batch_noalloc(const bm25_index* index, const int32_t* q_ids,
+                              const int64_t* q_offsets, int32_t n_queries, const int32_t* k,
+                              int32_t k_max, int32_t* out_ids, float* out_scores,
+                              int32_t* out_count, void* stream);
+
 /* Launch shape of the batched form. Zero fields mean "choose automatically".
  *   q_tile      queries sharing one workgroup's accumulators (1..64)
  *   waves       wavefronts per workgroup (1..16)

@@ -31,7 +31,8 @@ OK, E_INVAL, E_RANGE, E_NOMEM, E_BUSY, E_HIP, E_STATE, E_TIMEOUT = 0, -1, -2, -3
 # every symbol include/bm25.h declares
 EXPORTED = (
     "bm25_index_build", "bm25_index_info", "bm25_index_export", "bm25_index_device_bytes",
-    "bm25_index_range_stats", "bm25_index_free", "bm25_search_batch", "bm25_search_plain", "bm25_search_set_plan",
+    "bm25_index_range_stats", "bm25_index_free", "bm25_search_batch",
+    "bm25_search_batch_noalloc", "bm25_search_plain", "bm25_search_set_plan",
     "bm25_search_get_plan", "bm25_search_set_graphs", "bm25_search_graph_stats",
     "bm25_autotune", "bm25_kernel_timing", "bm25_kernel_time_read",
     "bm25_serve_create", "bm25_serve_submit", "bm25_serve_poll", "bm25_serve_stats",
@@ -134,7 +135,7 @@ def load_library() -> ctypes.CDLL:
     L.bm25_index_device_bytes.restype = i64
     L.bm25_index_free.argtypes = [vp]
     L.bm25_index_free.restype = None
-    for fn in (L.bm25_search_batch, L.bm25_search_plain):
+    for fn in (L.bm25_search_batch, L.bm25_search_plain, L.bm25_search_batch_noalloc):
         fn.argtypes = [vp, vp, vp, i32, vp, i32, vp, vp, vp, vp]
     L.bm25_search_set_plan.argtypes = [vp, P(TilePlan)]
     L.bm25_search_get_plan.argtypes = [vp, i32, i32, i32, P(TilePlan)]
@@ -328,6 +329,13 @@ class Index:
         """Batched form. q_ids: device int32; q_offsets: host int64[n+1]; k: int or int32[n]."""
         return self._search(load_library().bm25_search_batch, q_ids, q_offsets, k, k_max, out,
                             stream)
+
+    def search_batch_noalloc(self, q_ids, q_offsets, k=None, k_max=None, out=None,
+                             stream=None):
+        """Batched form on the library's fixed scratch: allocates nothing (pass `out` to keep
+        the call itself free of allocations)."""
+        return self._search(load_library().bm25_search_batch_noalloc, q_ids, q_offsets, k, k_max,
+                            out, stream)
 
     def search_plain(self, q_ids, q_offsets, k=None, k_max=None, out=None, stream=None):
         """Per-query form (one sweep launch per query)."""

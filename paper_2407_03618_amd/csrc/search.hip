@@ -816,9 +816,71 @@ int search_plain_impl(bm25_index* idx, const int32_t* q_ids, const int64_t* q_of
   return scratch_end(sc, s);
 }
 
+// Scratch of bm25_search_batch_noalloc. In host code `scratch` only names the array: its device
+// address comes from hipGetSymbolAddress, once per device (each device holds its own copy), and
+// only that address is handed to kernels or copies.
+static constexpr size_t kNoAllocScratchBytes = (size_t)BM25_NOALLOC_SCRATCH_BYTES;
+static __device__ __align__(256) uint8_t scratch[kNoAllocScratchBytes];
+static constexpr int kNoAllocMaxDevices = 64;
+static std::atomic<uint8_t*> g_scratch_ptr[kNoAllocMaxDevices];
+static std::mutex g_scratch_mu;
+// Host staging of the plan (pageable: hipMemcpyAsync has consumed it when it returns).
+static uint8_t g_noalloc_staging[(size_t)BM25_NOALLOC_MAX_QUERIES * 24 + 4096];
+
+static int noalloc_scratch(int device, uint8_t** ptr) {
+  if (device < 0 || device >= kNoAllocMaxDevices)
+    return set_error(BM25_E_INVAL, "device %d outside the %d devices served", device,
+                     kNoAllocMaxDevices);
+  uint8_t* p = g_scratch_ptr[device].load(std::memory_order_acquire);
+  if (!p) {
+    std::lock_guard<std::mutex> g(g_scratch_mu);
+    p = g_scratch_ptr[device].load(std::memory_order_acquire);
+    if (!p) {
+      void* a = nullptr;
+      const hipError_t e = hipGetSymbolAddress(&a, HIP_SYMBOL(scratch));
+      if (e != hipSuccess || !a)
+        return set_error(BM25_E_HIP, "hipGetSymbolAddress of the scratch array failed: %s",
+                         hipGetErrorString(e));
+      p = static_cast<uint8_t*>(a);
+      g_scratch_ptr[device].store(p, std::memory_order_release);
+    }
+  }
+  *ptr = p;
+  return BM25_OK;
+}
+
 }  // namespace bm25
 
 using namespace bm25;
+
+extern "C" int bm25_search_batch_noalloc(const bm25_index* index, const int32_t* q_ids,
+                                         const int64_t* q_offsets, int32_t n_queries,
+                                         const int32_t* k, int32_t k_max, int32_t* out_ids,
+                                         float* out_scores, int32_t* out_count, void* stream) {
+  clear_error();
+  if (!index) return set_error(BM25_E_INVAL, "index is NULL");
+  if (n_queries > BM25_NOALLOC_MAX_QUERIES)
+    return set_error(BM25_E_NOMEM, "%d queries exceed the %d this entry point plans without "
+                     "allocating", n_queries, BM25_NOALLOC_MAX_QUERIES);
+  int device = 0;
+  BM25_HIP(hipGetDevice(&device));
+  if (device != index->device)
+    return set_error(BM25_E_INVAL, "the index lives on device %d, the current device is %d",
+                     index->device, device);
+  uint8_t* base = nullptr;
+  int rc = noalloc_scratch(device, &base);
+  if (rc != BM25_OK) return rc;
+  bm25_index* idx = const_cast<bm25_index*>(index);
+  std::lock_guard<std::mutex> g(idx->mu);
+  SearchScratch sc;
+  sc.fixed = base;
+  sc.fixed_bytes = kNoAllocScratchBytes;
+  sc.host_fixed = g_noalloc_staging;
+  sc.host_fixed_bytes = sizeof(g_noalloc_staging);
+  sc.no_alloc = true;
+  return search_batch_impl(idx, q_ids, q_offsets, n_queries, k, k_max, out_ids, out_scores,
+                           out_count, (hipStream_t)stream, sc, nullptr);
+}
 
 extern "C" int bm25_search_batch(const bm25_index* index, const int32_t* q_ids,
                                  const int64_t* q_offsets, int32_t n_queries, const int32_t* k,
