@@ -4,8 +4,9 @@
 // Sparsity"; Section 2.1 for shifted variants):
 //   1. validate offsets and token ids on the device, |D| per document, sum |D| in int64;
 //   2. one 64-bit key per token position: (token << 32) | document;
-//   3. stable LSD radix sort of the keys by the token bits (8-bit digits); positions arrive in
-//      document order, so equal tokens stay ordered by document;
+//   3. stable LSD radix sort of the keys by the token bits (digits of at most 8 bits, each pass
+//      ranked in LDS and written out as contiguous runs); positions arrive in document order, so
+//      equal tokens stay ordered by document;
 //   4. run-length encoding of equal keys: one stored pair per distinct (t, D), TF = run length;
 //   5. indptr from the first pair of every token, DF = segment length, IDF in FP64;
 //   6. per-pair score S(t, D) (or S - S_theta) in FP32, rounded to the storage type;
@@ -211,11 +212,18 @@ __global__ __launch_bounds__(256) void k_make_keys(const int32_t* __restrict__ t
   }
 }
 
-// Stable LSD radix sort by 8-bit digits of the token. A block owns kRadixBlockItems keys; each of
-// its 4 waves owns a contiguous quarter, so the scatter order is (block, wave, position).
-constexpr int kRadixWaveItems = 64 * 64;
+// Stable LSD radix sort by digits of the token (at most 8 bits each). A block owns
+// kRadixBlockItems consecutive keys and each of its 4 waves a contiguous quarter, read 64 keys at a
+// time, so the order (wave, round, lane) is the index order. The histogram holds one count per
+// (digit, block), digit-major, so its exclusive scan gives every block the output start of each
+// digit. The scatter ranks its block's keys by digit in LDS (stable), then writes each digit's
+// keys as one contiguous run: consecutive lanes store to consecutive addresses.
+constexpr int kRadixRounds = 16;
+constexpr int kRadixWaveItems = 64 * kRadixRounds;
 constexpr int kRadixBlockItems = 4 * kRadixWaveItems;
+constexpr int kRadixBuckets = 256;
 
+// Lanes whose digit equals this lane's (bits above the digit width are zero in every lane).
 __device__ __forceinline__ uint64_t match_digit8(uint32_t d) {
   uint64_t m = ~0ull;
 #pragma unroll
@@ -228,52 +236,89 @@ __device__ __forceinline__ uint64_t match_digit8(uint32_t d) {
 }
 
 __global__ __launch_bounds__(256) void k_radix_hist(const uint64_t* __restrict__ keys, int64_t n,
-                                                    int shift, uint32_t* __restrict__ hist,
-                                                    int64_t nblk) {
-  __shared__ uint32_t h[4][256];
-  for (int i = threadIdx.x; i < 1024; i += 256) (&h[0][0])[i] = 0;
+                                                    int shift, uint32_t mask,
+                                                    uint32_t* __restrict__ hist, int64_t nblk) {
+  __shared__ uint32_t h[kRadixBuckets];
+  h[threadIdx.x] = 0;
   __syncthreads();
   const int w = threadIdx.x >> 6;
   const int l = lane();
   const int64_t base = (int64_t)blockIdx.x * kRadixBlockItems + (int64_t)w * kRadixWaveItems;
-  for (int r = 0; r < kRadixWaveItems / 64; ++r) {
+  for (int r = 0; r < kRadixRounds; ++r) {
     const int64_t i = base + r * 64 + l;
     const bool valid = i < n;
-    const uint32_t d = valid ? (uint32_t)(keys[i] >> shift) & 255u : 0u;
+    const uint32_t d = valid ? (uint32_t)(keys[i] >> shift) & mask : 0u;
     const uint64_t peers = match_digit8(d) & ballot(valid);
-    if (valid && __builtin_ctzll(peers) == l) atomicAdd(&h[w][d], (uint32_t)__popcll(peers));
+    if (valid && __builtin_ctzll(peers) == l) atomicAdd(&h[d], (uint32_t)__popcll(peers));
   }
   __syncthreads();
-  for (int i = threadIdx.x; i < 1024; i += 256) {
-    const int ww = i >> 8, d = i & 255;
-    hist[((int64_t)d * nblk + blockIdx.x) * 4 + ww] = h[ww][d];
-  }
+  hist[(int64_t)threadIdx.x * nblk + blockIdx.x] = h[threadIdx.x];
 }
 
 __global__ __launch_bounds__(256) void k_radix_scatter(const uint64_t* __restrict__ in,
                                                        uint64_t* __restrict__ out, int64_t n,
-                                                       int shift,
+                                                       int shift, uint32_t mask,
                                                        const uint32_t* __restrict__ pos,
                                                        int64_t nblk) {
-  __shared__ uint32_t run[4][256];
-  for (int i = threadIdx.x; i < 1024; i += 256) {
-    const int ww = i >> 8, d = i & 255;
-    run[ww][d] = pos[((int64_t)d * nblk + blockIdx.x) * 4 + ww];
+  __shared__ uint64_t sk[kRadixBlockItems];      // the block's keys in digit order
+  __shared__ uint32_t cnt[4][kRadixBuckets];     // per wave: keys of each digit
+  __shared__ uint32_t dstart[kRadixBuckets];     // block-local start of each digit
+  __shared__ uint32_t gstart[kRadixBuckets];     // output start of each digit for this block
+  __shared__ uint32_t scan4[4];
+  const int t = threadIdx.x;
+  const int w = t >> 6;
+  const int l = lane();
+#pragma unroll
+  for (int ww = 0; ww < 4; ++ww) cnt[ww][t] = 0;
+  gstart[t] = pos[(int64_t)t * nblk + blockIdx.x];
+  const int64_t blk0 = (int64_t)blockIdx.x * kRadixBlockItems;
+  const int64_t base = blk0 + (int64_t)w * kRadixWaveItems;
+  uint64_t key[kRadixRounds];
+#pragma unroll
+  for (int r = 0; r < kRadixRounds; ++r) {
+    const int64_t i = base + r * 64 + l;
+    key[r] = (i < n) ? in[i] : 0ull;
   }
   __syncthreads();
-  const int w = threadIdx.x >> 6;
-  const int l = lane();
-  const int64_t base = (int64_t)blockIdx.x * kRadixBlockItems + (int64_t)w * kRadixWaveItems;
+  // rank of each key among the wave's keys of its digit, in index order
   const uint64_t lt = lanemask_lt();
-  for (int r = 0; r < kRadixWaveItems / 64; ++r) {
-    const int64_t i = base + r * 64 + l;
-    const bool valid = i < n;
-    const uint64_t key = valid ? in[i] : 0ull;
-    const uint32_t d = (uint32_t)(key >> shift) & 255u;
+  uint32_t rk[kRadixRounds];
+#pragma unroll
+  for (int r = 0; r < kRadixRounds; ++r) {
+    const bool valid = base + r * 64 + l < n;
+    const uint32_t d = (uint32_t)(key[r] >> shift) & mask;
     const uint64_t peers = match_digit8(d) & ballot(valid);
-    const uint32_t p0 = run[w][d];
-    if (valid) out[p0 + (uint32_t)__popcll(peers & lt)] = key;
-    if (valid && __builtin_ctzll(peers) == l) run[w][d] = p0 + (uint32_t)__popcll(peers);
+    const uint32_t c0 = cnt[w][d];
+    rk[r] = c0 + (uint32_t)__popcll(peers & lt);
+    if (valid && __builtin_ctzll(peers) == l) cnt[w][d] = c0 + (uint32_t)__popcll(peers);
+  }
+  __syncthreads();
+  // thread t = digit t: the waves' counts become exclusive prefixes, dstart the digit starts
+  {
+    uint32_t run = 0;
+#pragma unroll
+    for (int ww = 0; ww < 4; ++ww) {
+      const uint32_t c = cnt[ww][t];
+      cnt[ww][t] = run;
+      run += c;
+    }
+    uint32_t tot;
+    dstart[t] = block_exclusive_scan<uint32_t>(run, scan4, tot);
+  }
+  __syncthreads();
+#pragma unroll
+  for (int r = 0; r < kRadixRounds; ++r) {
+    if (base + r * 64 + l < n) {
+      const uint32_t d = (uint32_t)(key[r] >> shift) & mask;
+      sk[dstart[d] + cnt[w][d] + rk[r]] = key[r];
+    }
+  }
+  __syncthreads();
+  const int64_t nb = (n - blk0 < kRadixBlockItems) ? n - blk0 : kRadixBlockItems;
+  for (int i = t; i < nb; i += 256) {
+    const uint64_t k = sk[i];
+    const uint32_t d = (uint32_t)(k >> shift) & mask;
+    out[(int64_t)gstart[d] + (i - (int64_t)dstart[d])] = k;
   }
 }
 
@@ -604,8 +649,10 @@ extern "C" int bm25_index_build(const int32_t* token_ids, int64_t n_tokens,
   // 3. stable LSD radix sort by token digits
   const int tbits = bits_needed((uint32_t)(V - 1));
   const int passes = (tbits + 7) / 8;
+  const int dbits = passes > 0 ? (tbits + passes - 1) / passes : 0;  // digit width, <= 8
+  const uint32_t dmask = (1u << dbits) - 1u;
   const int64_t nblk = (T + kRadixBlockItems - 1) / kRadixBlockItems;
-  const int64_t hn = nblk * 1024;
+  const int64_t hn = nblk * kRadixBuckets;
   DevBuf hist(al), tmp(al);
   BM25_ALLOC(hist, (size_t)hn * 4);
   const int64_t nrb = (T + kRleBlockItems - 1) / kRleBlockItems;
@@ -614,14 +661,14 @@ extern "C" int bm25_index_build(const int32_t* token_ids, int64_t n_tokens,
   uint64_t* src = ka.as<uint64_t>();
   uint64_t* dst = kb.as<uint64_t>();
   for (int pass = 0; pass < passes; ++pass) {
-    const int shift = 32 + 8 * pass;
-    hipLaunchKernelGGL(k_radix_hist, dim3((unsigned)nblk), dim3(256), 0, s, src, T, shift,
+    const int shift = 32 + dbits * pass;
+    hipLaunchKernelGGL(k_radix_hist, dim3((unsigned)nblk), dim3(256), 0, s, src, T, shift, dmask,
                        hist.as<uint32_t>(), nblk);
     BM25_HIP(hipGetLastError());
     BM25_HIP(scan_exclusive<uint32_t>(hist.as<uint32_t>(), hist.as<uint32_t>(), hn,
                                       tmp.as<uint32_t>(), nullptr, s));
     hipLaunchKernelGGL(k_radix_scatter, dim3((unsigned)nblk), dim3(256), 0, s, src, dst, T, shift,
-                       hist.as<uint32_t>(), nblk);
+                       dmask, hist.as<uint32_t>(), nblk);
     BM25_HIP(hipGetLastError());
     std::swap(src, dst);
   }
