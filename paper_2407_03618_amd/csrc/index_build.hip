@@ -165,8 +165,28 @@ template hipError_t scan_exclusive<int64_t>(const int64_t*, int64_t*, int64_t, i
 struct BuildStatus {
   unsigned long long sum_len;
   unsigned int flags;  // 1: malformed offsets, 2: token id out of range, 4: document too long
-  unsigned int pad;
+  unsigned int max_len;  // longest document (clamped to 2^31 - 1)
 };
+
+// Layout of the 64-bit sort key of a token position, from the top: token | document | |D|.
+// The document length rides in the low bits when the bits left over by the token and document
+// ids hold the longest document (len_bits > 0); the score then reads it from the key instead of
+// gathering doclen[d] for every stored pair. Equal (token, document) keys are equal keys either
+// way, since |D| is a function of the document.
+struct KeyLayout {
+  int tok_shift;      // token = key >> tok_shift
+  int doc_shift;      // document = (key >> doc_shift) & doc_mask
+  uint64_t doc_mask;
+  uint32_t len_mask;  // |D| = key & len_mask when len_bits > 0
+  int len_bits;
+};
+
+__device__ __forceinline__ uint32_t key_token(uint64_t k, const KeyLayout& L) {
+  return (uint32_t)(k >> L.tok_shift);
+}
+__device__ __forceinline__ uint32_t key_doc(uint64_t k, const KeyLayout& L) {
+  return (uint32_t)((k >> L.doc_shift) & L.doc_mask);
+}
 
 __device__ __forceinline__ uint64_t wave_sum_u64(uint64_t v) {
 #pragma unroll
@@ -182,12 +202,15 @@ __global__ __launch_bounds__(256) void k_validate(const int32_t* __restrict__ to
   const int64_t stride = (int64_t)gridDim.x * blockDim.x;
   uint64_t local = 0;
   unsigned flags = 0;
+  unsigned mx = 0;
   for (int64_t d = gid; d < N; d += stride) {
     const int64_t lo = off[d], hi = off[d + 1];
     const int64_t len = hi - lo;
     if (len < 0 || lo < 0 || hi > T) flags |= 1u;
     if (len > (int64_t)INT32_MAX) flags |= 4u;
-    doclen[d] = (int32_t)(len < 0 ? 0 : (len > INT32_MAX ? INT32_MAX : len));
+    const int32_t lc = (int32_t)(len < 0 ? 0 : (len > INT32_MAX ? INT32_MAX : len));
+    doclen[d] = lc;
+    mx = mx > (unsigned)lc ? mx : (unsigned)lc;
     local += (uint64_t)(len > 0 ? len : 0);
   }
   if (gid == 0 && (off[0] != 0 || off[N] != T)) flags |= 1u;
@@ -197,18 +220,26 @@ __global__ __launch_bounds__(256) void k_validate(const int32_t* __restrict__ to
   }
   local = wave_sum_u64(local);
   if (lane() == 0 && local) atomicAdd(&st->sum_len, (unsigned long long)local);
+#pragma unroll
+  for (int o = 32; o > 0; o >>= 1) {
+    const unsigned y = bperm(mx, lane() ^ o);
+    mx = mx > y ? mx : y;
+  }
+  if (lane() == 0 && mx) atomicMax(&st->max_len, mx);
   if (flags) atomicOr(&st->flags, flags);
 }
 
-// One key per position: the token in the high half, the document in the low half.
+// One key per position (KeyLayout).
 __global__ __launch_bounds__(256) void k_make_keys(const int32_t* __restrict__ tok,
                                                    const int64_t* __restrict__ off, int64_t N,
-                                                   uint64_t* __restrict__ keys) {
+                                                   KeyLayout L, uint64_t* __restrict__ keys) {
   const int64_t nwaves = (int64_t)gridDim.x * (blockDim.x / 64);
   for (int64_t d = ((int64_t)blockIdx.x * blockDim.x + threadIdx.x) / 64; d < N; d += nwaves) {
     const int64_t lo = off[d], hi = off[d + 1];
+    const uint64_t dl = ((uint64_t)(uint32_t)d << L.doc_shift) |
+                        (L.len_bits > 0 ? (uint64_t)(hi - lo) : 0ull);
     for (int64_t p = lo + lane(); p < hi; p += 64)
-      keys[p] = ((uint64_t)(uint32_t)tok[p] << 32) | (uint64_t)(uint32_t)d;
+      keys[p] = ((uint64_t)(uint32_t)tok[p] << L.tok_shift) | dl;
   }
 }
 
@@ -367,11 +398,12 @@ __global__ void k_set_u32(uint32_t* p, uint32_t v) { *p = v; }
 
 // indptr[t] = first stored pair whose token is >= t, for t in [0, V].
 __global__ __launch_bounds__(256) void k_indptr(const uint64_t* __restrict__ uniq, int64_t nnz,
-                                                int32_t V, int64_t* __restrict__ indptr) {
+                                                int32_t V, KeyLayout L,
+                                                int64_t* __restrict__ indptr) {
   const int64_t j = (int64_t)blockIdx.x * blockDim.x + threadIdx.x;
   if (j > nnz) return;
-  const int64_t cur = (j < nnz) ? (int64_t)(uniq[j] >> 32) : (int64_t)V;
-  const int64_t prev = (j > 0) ? (int64_t)(uniq[j - 1] >> 32) : -1;
+  const int64_t cur = (j < nnz) ? (int64_t)key_token(uniq[j], L) : (int64_t)V;
+  const int64_t prev = (j > 0) ? (int64_t)key_token(uniq[j - 1], L) : -1;
   for (int64_t t = prev + 1; t <= cur; ++t) indptr[t] = j;
 }
 
@@ -478,6 +510,7 @@ __global__ __launch_bounds__(256) void k_score(const uint64_t* __restrict__ uniq
                                                const uint32_t* __restrict__ starts, int64_t nnz,
                                                const int32_t* __restrict__ doclen,
                                                const double* __restrict__ idf, ScoreParams p,
+                                               KeyLayout L,
                                                int32_t* __restrict__ indices,
                                                int32_t* __restrict__ tf_out,
                                                typename ST::T* __restrict__ data,
@@ -486,13 +519,14 @@ __global__ __launch_bounds__(256) void k_score(const uint64_t* __restrict__ uniq
   uint32_t cls = 0;
   if (j < nnz) {
     const uint64_t key = uniq[j];
-    const uint32_t t = (uint32_t)(key >> 32);
-    const uint32_t d = (uint32_t)key;
+    const uint32_t t = key_token(key, L);
+    const uint32_t d = key_doc(key, L);
     const uint32_t tf = starts[j + 1] - starts[j];
     indices[j] = (int32_t)d;
     tf_out[j] = (int32_t)tf;
     const float w = (float)idf[t];
-    const float x = w * stored_factor((float)tf, (float)doclen[d], p);
+    const uint32_t len = (L.len_bits > 0) ? (uint32_t)key & L.len_mask : (uint32_t)doclen[d];
+    const float x = w * stored_factor((float)tf, (float)len, p);
     const typename ST::T v = ST::store(x);
     data[j] = v;
     cls = range_class<ST>(x, v);
@@ -508,13 +542,13 @@ __global__ __launch_bounds__(256) void k_score(const uint64_t* __restrict__ uniq
 // Skip table of long rows: skip[lid][b] = offset inside the row of the first entry whose
 // document id is >= b * kSkipBlock (the row length if none), for b in [0, nblocks].
 __global__ __launch_bounds__(256) void k_skip(const uint64_t* __restrict__ uniq, int64_t nnz,
-                                              const int32_t* __restrict__ indices,
+                                              KeyLayout L, const int32_t* __restrict__ indices,
                                               const int64_t* __restrict__ indptr,
                                               const int32_t* __restrict__ long_id,
                                               int64_t nblocks, uint32_t* __restrict__ skip) {
   const int64_t j = (int64_t)blockIdx.x * blockDim.x + threadIdx.x;
   if (j >= nnz) return;
-  const uint32_t t = (uint32_t)(uniq[j] >> 32);
+  const uint32_t t = key_token(uniq[j], L);
   const int32_t lid = long_id[t];
   if (lid < 0) return;
   const int64_t lo = indptr[t], hi = indptr[t + 1];
@@ -529,16 +563,16 @@ __global__ __launch_bounds__(256) void k_skip(const uint64_t* __restrict__ uniq,
 // Dense rows: dense[h][d] = stored score of (t, d) for the dense tokens t (row h = dense_id[t]).
 template <typename T>
 __global__ __launch_bounds__(256) void k_dense_scatter(const uint64_t* __restrict__ uniq,
-                                                       int64_t nnz,
+                                                       int64_t nnz, KeyLayout L,
                                                        const int32_t* __restrict__ dense_id,
                                                        const T* __restrict__ data, int64_t n_pad,
                                                        T* __restrict__ dense) {
   const int64_t j = (int64_t)blockIdx.x * blockDim.x + threadIdx.x;
   if (j >= nnz) return;
   const uint64_t key = uniq[j];
-  const int32_t h = dense_id[(uint32_t)(key >> 32)];
+  const int32_t h = dense_id[key_token(key, L)];
   if (h < 0) return;
-  dense[(int64_t)h * n_pad + (uint32_t)key] = data[j];
+  dense[(int64_t)h * n_pad + key_doc(key, L)] = data[j];
 }
 
 static unsigned grid_for(int64_t n, int threads) {
@@ -639,15 +673,25 @@ extern "C" int bm25_index_build(const int32_t* token_ids, int64_t n_tokens,
   idx->l_avg = (double)idx->sum_len / (double)N;
 
   // 2. keys
+  const int tbits = bits_needed((uint32_t)(V - 1));
+  KeyLayout kl;
+  {
+    const int dbits_doc = std::max(1, bits_needed((uint32_t)(N - 1)));
+    const int lbits = std::max(1, bits_needed(hst.max_len));
+    kl.len_bits = (tbits + dbits_doc + lbits <= 64) ? lbits : 0;
+    kl.len_mask = kl.len_bits > 0 ? (uint32_t)((1ull << kl.len_bits) - 1) : 0u;
+    kl.doc_shift = kl.len_bits;
+    kl.doc_mask = (1ull << dbits_doc) - 1;
+    kl.tok_shift = kl.len_bits + dbits_doc;
+  }
   DevBuf ka(al), kb(al);
   BM25_ALLOC(ka, (size_t)T * 8);
   BM25_ALLOC(kb, (size_t)T * 8);
   hipLaunchKernelGGL(k_make_keys, dim3((unsigned)std::min<int64_t>(grid_for(N * 64, 256), 65536)),
-                     dim3(256), 0, s, token_ids, doc_offsets, N, ka.as<uint64_t>());
+                     dim3(256), 0, s, token_ids, doc_offsets, N, kl, ka.as<uint64_t>());
   BM25_HIP(hipGetLastError());
 
   // 3. stable LSD radix sort by token digits
-  const int tbits = bits_needed((uint32_t)(V - 1));
   const int passes = (tbits + 7) / 8;
   const int dbits = passes > 0 ? (tbits + passes - 1) / passes : 0;  // digit width, <= 8
   const uint32_t dmask = (1u << dbits) - 1u;
@@ -661,7 +705,7 @@ extern "C" int bm25_index_build(const int32_t* token_ids, int64_t n_tokens,
   uint64_t* src = ka.as<uint64_t>();
   uint64_t* dst = kb.as<uint64_t>();
   for (int pass = 0; pass < passes; ++pass) {
-    const int shift = 32 + dbits * pass;
+    const int shift = kl.tok_shift + dbits * pass;
     hipLaunchKernelGGL(k_radix_hist, dim3((unsigned)nblk), dim3(256), 0, s, src, T, shift, dmask,
                        hist.as<uint32_t>(), nblk);
     BM25_HIP(hipGetLastError());
@@ -704,7 +748,7 @@ extern "C" int bm25_index_build(const int32_t* token_ids, int64_t n_tokens,
   BM25_ALLOC(idx->theta, (size_t)V * 8);
   BM25_ALLOC(idx->theta32, (size_t)V * 4);
   BM25_ALLOC(idx->long_id, (size_t)V * 4);
-  hipLaunchKernelGGL(k_indptr, dim3(grid_for(nnz + 1, 256)), dim3(256), 0, s, uniq, nnz, V,
+  hipLaunchKernelGGL(k_indptr, dim3(grid_for(nnz + 1, 256)), dim3(256), 0, s, uniq, nnz, V, kl,
                      idx->indptr.as<int64_t>());
   BM25_HIP(hipGetLastError());
   DevBuf is_long(al), long_excl(al);
@@ -737,19 +781,19 @@ extern "C" int bm25_index_build(const int32_t* token_ids, int64_t n_tokens,
     switch (P.store_dtype) {
       case BM25_F32:
         hipLaunchKernelGGL(k_score<F32>, dim3(g), dim3(256), 0, s, uniq, starts.as<uint32_t>(),
-                           nnz, idx->doclen.as<int32_t>(), idx->idf.as<double>(), sp,
+                           nnz, idx->doclen.as<int32_t>(), idx->idf.as<double>(), sp, kl,
                            idx->indices.as<int32_t>(), idx->tf.as<int32_t>(),
                            idx->data.as<float>(), range_dev);
         break;
       case BM25_F16:
         hipLaunchKernelGGL(k_score<F16>, dim3(g), dim3(256), 0, s, uniq, starts.as<uint32_t>(),
-                           nnz, idx->doclen.as<int32_t>(), idx->idf.as<double>(), sp,
+                           nnz, idx->doclen.as<int32_t>(), idx->idf.as<double>(), sp, kl,
                            idx->indices.as<int32_t>(), idx->tf.as<int32_t>(),
                            idx->data.as<__half>(), range_dev);
         break;
       default:
         hipLaunchKernelGGL(k_score<BF16>, dim3(g), dim3(256), 0, s, uniq, starts.as<uint32_t>(),
-                           nnz, idx->doclen.as<int32_t>(), idx->idf.as<double>(), sp,
+                           nnz, idx->doclen.as<int32_t>(), idx->idf.as<double>(), sp, kl,
                            idx->indices.as<int32_t>(), idx->tf.as<int32_t>(),
                            idx->data.as<uint16_t>(), range_dev);
     }
@@ -769,7 +813,7 @@ extern "C" int bm25_index_build(const int32_t* token_ids, int64_t n_tokens,
   idx->n_blocks = (N + kSkipBlock - 1) / kSkipBlock;
   BM25_ALLOC(idx->skip, (size_t)std::max<int64_t>(1, (int64_t)n_long * (idx->n_blocks + 1)) * 4);
   if (n_long > 0) {
-    hipLaunchKernelGGL(k_skip, dim3(grid_for(nnz, 256)), dim3(256), 0, s, uniq, nnz,
+    hipLaunchKernelGGL(k_skip, dim3(grid_for(nnz, 256)), dim3(256), 0, s, uniq, nnz, kl,
                        idx->indices.as<int32_t>(), idx->indptr.as<int64_t>(),
                        idx->long_id.as<int32_t>(), idx->n_blocks, idx->skip.as<uint32_t>());
     BM25_HIP(hipGetLastError());
@@ -810,11 +854,11 @@ extern "C" int bm25_index_build(const int32_t* token_ids, int64_t n_tokens,
       BM25_HIP(hipMemsetAsync(idx->dense.ptr, 0, dbytes, s));
       const unsigned g = grid_for(nnz, 256);
       if (sb == 4)
-        hipLaunchKernelGGL(k_dense_scatter<uint32_t>, dim3(g), dim3(256), 0, s, uniq, nnz,
+        hipLaunchKernelGGL(k_dense_scatter<uint32_t>, dim3(g), dim3(256), 0, s, uniq, nnz, kl,
                            idx->dense_id.as<int32_t>(), idx->data.as<uint32_t>(), idx->n_pad,
                            idx->dense.as<uint32_t>());
       else
-        hipLaunchKernelGGL(k_dense_scatter<uint16_t>, dim3(g), dim3(256), 0, s, uniq, nnz,
+        hipLaunchKernelGGL(k_dense_scatter<uint16_t>, dim3(g), dim3(256), 0, s, uniq, nnz, kl,
                            idx->dense_id.as<int32_t>(), idx->data.as<uint16_t>(), idx->n_pad,
                            idx->dense.as<uint16_t>());
       BM25_HIP(hipGetLastError());
