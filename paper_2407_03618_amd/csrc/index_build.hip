@@ -436,7 +436,9 @@ __global__ __launch_bounds__(256) void k_df_idf(const int64_t* __restrict__ indp
                                                 double* __restrict__ idf,
                                                 double* __restrict__ theta,
                                                 float* __restrict__ theta32,
-                                                uint32_t* __restrict__ is_long) {
+                                                uint32_t* __restrict__ is_long,
+                                                int64_t min_dense_df,
+                                                uint32_t* __restrict__ is_dense) {
   const int64_t t = (int64_t)blockIdx.x * blockDim.x + threadIdx.x;
   if (t >= V) return;
   const int64_t d = indptr[t + 1] - indptr[t];
@@ -447,6 +449,31 @@ __global__ __launch_bounds__(256) void k_df_idf(const int64_t* __restrict__ indp
   theta[t] = th;
   theta32[t] = (float)th;
   is_long[t] = (d >= kLongRow) ? 1u : 0u;
+  is_dense[t] = (d >= min_dense_df) ? 1u : 0u;
+}
+
+// Tokens flagged as dense-row candidates, compacted in token order with their document
+// frequencies (the choice among them is made on the host: there are few).
+__global__ void k_dense_candidates(const uint32_t* __restrict__ flag,
+                                   const uint32_t* __restrict__ excl,
+                                   const int32_t* __restrict__ df, int32_t V,
+                                   int32_t* __restrict__ cand_tok, int32_t* __restrict__ cand_df) {
+  const int64_t t = (int64_t)blockIdx.x * blockDim.x + threadIdx.x;
+  if (t >= V || !flag[t]) return;
+  cand_tok[excl[t]] = (int32_t)t;
+  cand_df[excl[t]] = df[t];
+}
+
+// dense_id[tok[i]] = i for the chosen dense-row tokens (dense_id holds -1 elsewhere).
+__global__ void k_set_dense_ids(const int32_t* __restrict__ tok, int32_t n,
+                                int32_t* __restrict__ dense_id) {
+  const int i = blockIdx.x * blockDim.x + threadIdx.x;
+  if (i < n) dense_id[tok[i]] = i;
+}
+
+__global__ void k_fill_i32(int32_t* __restrict__ p, int64_t n, int32_t v) {
+  const int64_t i = (int64_t)blockIdx.x * blockDim.x + threadIdx.x;
+  if (i < n) p[i] = v;
 }
 
 __global__ void k_long_id(const uint32_t* __restrict__ flag, const uint32_t* __restrict__ excl,
@@ -505,6 +532,22 @@ __device__ __forceinline__ uint32_t range_class(float x, typename ST::T v) {
   return c;
 }
 
+struct SkipOut {
+  const int32_t* long_id;
+  const int64_t* indptr;
+  int64_t nblocks;
+  uint32_t* skip;
+};
+
+template <typename T>
+struct DenseOut {
+  const int32_t* dense_id;  // dense row of each token or -1
+  int64_t n_pad;
+  T* dense;
+};
+
+// Per stored pair: document id, TF, stored score and its range class; the pair's entries in the
+// skip table (long rows) and its value in the dense rows (dense-row tokens).
 template <typename ST>
 __global__ __launch_bounds__(256) void k_score(const uint64_t* __restrict__ uniq,
                                                const uint32_t* __restrict__ starts, int64_t nnz,
@@ -514,7 +557,8 @@ __global__ __launch_bounds__(256) void k_score(const uint64_t* __restrict__ uniq
                                                int32_t* __restrict__ indices,
                                                int32_t* __restrict__ tf_out,
                                                typename ST::T* __restrict__ data,
-                                               unsigned long long* __restrict__ range) {
+                                               unsigned long long* __restrict__ range,
+                                               SkipOut sko, DenseOut<typename ST::T> dno) {
   const int64_t j = (int64_t)blockIdx.x * blockDim.x + threadIdx.x;
   uint32_t cls = 0;
   if (j < nnz) {
@@ -530,6 +574,21 @@ __global__ __launch_bounds__(256) void k_score(const uint64_t* __restrict__ uniq
     const typename ST::T v = ST::store(x);
     data[j] = v;
     cls = range_class<ST>(x, v);
+    // skip table: skip[lid][b] = offset inside the row of the first entry whose document id is
+    // >= b * kSkipBlock (the row length if none), for b in [0, nblocks]
+    const int32_t lid = sko.long_id[t];
+    if (lid >= 0) {
+      const int64_t lo = sko.indptr[t], hi = sko.indptr[t + 1];
+      uint32_t* row = sko.skip + (int64_t)lid * (sko.nblocks + 1);
+      const int64_t blk = (int64_t)d / kSkipBlock;
+      const int64_t prev = (j == lo) ? -1 : (int64_t)key_doc(uniq[j - 1], L) / kSkipBlock;
+      for (int64_t b = prev + 1; b <= blk; ++b) row[b] = (uint32_t)(j - lo);
+      if (j == hi - 1)
+        for (int64_t b = blk + 1; b <= sko.nblocks; ++b) row[b] = (uint32_t)(hi - lo);
+    }
+    // dense rows: dense[h][d] = stored score of (t, d) for the dense tokens t
+    const int32_t h = dno.dense_id[t];
+    if (h >= 0) dno.dense[(int64_t)h * dno.n_pad + d] = v;
   }
   // one atomic per wave and class that occurs (almost never)
 #pragma unroll
@@ -537,42 +596,6 @@ __global__ __launch_bounds__(256) void k_score(const uint64_t* __restrict__ uniq
     const uint64_t m = ballot((cls >> c) & 1u);
     if (m != 0 && lane() == 0) atomicAdd(range + c, (unsigned long long)__popcll(m));
   }
-}
-
-// Skip table of long rows: skip[lid][b] = offset inside the row of the first entry whose
-// document id is >= b * kSkipBlock (the row length if none), for b in [0, nblocks].
-__global__ __launch_bounds__(256) void k_skip(const uint64_t* __restrict__ uniq, int64_t nnz,
-                                              KeyLayout L, const int32_t* __restrict__ indices,
-                                              const int64_t* __restrict__ indptr,
-                                              const int32_t* __restrict__ long_id,
-                                              int64_t nblocks, uint32_t* __restrict__ skip) {
-  const int64_t j = (int64_t)blockIdx.x * blockDim.x + threadIdx.x;
-  if (j >= nnz) return;
-  const uint32_t t = key_token(uniq[j], L);
-  const int32_t lid = long_id[t];
-  if (lid < 0) return;
-  const int64_t lo = indptr[t], hi = indptr[t + 1];
-  uint32_t* row = skip + (int64_t)lid * (nblocks + 1);
-  const int64_t blk = indices[j] / kSkipBlock;
-  const int64_t prev = (j == lo) ? -1 : indices[j - 1] / kSkipBlock;
-  for (int64_t b = prev + 1; b <= blk; ++b) row[b] = (uint32_t)(j - lo);
-  if (j == hi - 1)
-    for (int64_t b = blk + 1; b <= nblocks; ++b) row[b] = (uint32_t)(hi - lo);
-}
-
-// Dense rows: dense[h][d] = stored score of (t, d) for the dense tokens t (row h = dense_id[t]).
-template <typename T>
-__global__ __launch_bounds__(256) void k_dense_scatter(const uint64_t* __restrict__ uniq,
-                                                       int64_t nnz, KeyLayout L,
-                                                       const int32_t* __restrict__ dense_id,
-                                                       const T* __restrict__ data, int64_t n_pad,
-                                                       T* __restrict__ dense) {
-  const int64_t j = (int64_t)blockIdx.x * blockDim.x + threadIdx.x;
-  if (j >= nnz) return;
-  const uint64_t key = uniq[j];
-  const int32_t h = dense_id[key_token(key, L)];
-  if (h < 0) return;
-  dense[(int64_t)h * n_pad + key_doc(key, L)] = data[j];
 }
 
 static unsigned grid_for(int64_t n, int threads) {
@@ -741,7 +764,7 @@ extern "C" int bm25_index_build(const int32_t* token_ids, int64_t n_tokens,
   hipLaunchKernelGGL(k_set_u32, dim3(1), dim3(1), 0, s, starts.as<uint32_t>() + nnz, (uint32_t)T);
   BM25_HIP(hipGetLastError());
 
-  // 5. indptr, DF, IDF, S_theta, long rows
+  // 5. indptr, DF, IDF, S_theta, long rows, dense-row candidates
   BM25_ALLOC(idx->indptr, ((size_t)V + 1) * 8);
   BM25_ALLOC(idx->df, (size_t)V * 4);
   BM25_ALLOC(idx->idf, (size_t)V * 8);
@@ -751,24 +774,93 @@ extern "C" int bm25_index_build(const int32_t* token_ids, int64_t n_tokens,
   hipLaunchKernelGGL(k_indptr, dim3(grid_for(nnz + 1, 256)), dim3(256), 0, s, uniq, nnz, V, kl,
                      idx->indptr.as<int64_t>());
   BM25_HIP(hipGetLastError());
-  DevBuf is_long(al), long_excl(al);
+  const int64_t min_dense_df = std::max<int64_t>(2, (N + kDenseFraction - 1) / kDenseFraction);
+  DevBuf is_long(al), long_excl(al), is_dense(al), dense_excl(al);
   BM25_ALLOC(is_long, (size_t)V * 4);
   BM25_ALLOC(long_excl, (size_t)V * 4);
+  BM25_ALLOC(is_dense, (size_t)V * 4);
+  BM25_ALLOC(dense_excl, (size_t)V * 4);
   hipLaunchKernelGGL(k_df_idf, dim3(grid_for(V, 256)), dim3(256), 0, s,
                      idx->indptr.as<int64_t>(), V, (double)N, P.variant, P.k1, P.delta,
                      idx->df.as<int32_t>(), idx->idf.as<double>(), idx->theta.as<double>(),
-                     idx->theta32.as<float>(), is_long.as<uint32_t>());
+                     idx->theta32.as<float>(), is_long.as<uint32_t>(), min_dense_df,
+                     is_dense.as<uint32_t>());
   BM25_HIP(hipGetLastError());
   BM25_HIP(scan_exclusive<uint32_t>(is_long.as<uint32_t>(), long_excl.as<uint32_t>(), V,
                                     tmp.as<uint32_t>(), total.as<uint32_t>() + 1, s));
   hipLaunchKernelGGL(k_long_id, dim3(grid_for(V, 256)), dim3(256), 0, s, is_long.as<uint32_t>(),
                      long_excl.as<uint32_t>(), V, idx->long_id.as<int32_t>());
   BM25_HIP(hipGetLastError());
+  BM25_HIP(scan_exclusive<uint32_t>(is_dense.as<uint32_t>(), dense_excl.as<uint32_t>(), V,
+                                    tmp.as<uint32_t>(), total.as<uint32_t>() + 2, s));
+  // candidate lists in the long-row scratch, which the long ids no longer need
+  int32_t* cand_tok = reinterpret_cast<int32_t*>(is_long.ptr);
+  int32_t* cand_df = reinterpret_cast<int32_t*>(long_excl.ptr);
+  hipLaunchKernelGGL(k_dense_candidates, dim3(grid_for(V, 256)), dim3(256), 0, s,
+                     is_dense.as<uint32_t>(), dense_excl.as<uint32_t>(), idx->df.as<int32_t>(), V,
+                     cand_tok, cand_df);
+  BM25_HIP(hipGetLastError());
+  uint32_t counts_h[2] = {0, 0};  // long rows, dense-row candidates
+  BM25_HIP(hipMemcpyAsync(counts_h, total.as<uint32_t>() + 1, 8, hipMemcpyDeviceToHost, s));
+  BM25_HIP(hipStreamSynchronize(s));
+  const uint32_t n_long = counts_h[0];
+  const uint32_t n_cand = counts_h[1];
 
-  // 6. per-pair scores
+  // 6. dense rows of the most frequent tokens: the candidates are few (a token in at least 1/16
+  //    of the documents), so the choice runs on the host. The rows are kept in token order, so
+  //    that the layout does not depend on tie order.
+  const int64_t sb = (int64_t)store_bytes(P.store_dtype);
+  idx->n_pad = ((N + kDensePad - 1) / kDensePad) * kDensePad;
+  {
+    std::vector<int32_t> ct(n_cand), cd(n_cand);
+    if (n_cand > 0) {
+      BM25_HIP(hipMemcpyAsync(ct.data(), cand_tok, (size_t)n_cand * 4, hipMemcpyDeviceToHost, s));
+      BM25_HIP(hipMemcpyAsync(cd.data(), cand_df, (size_t)n_cand * 4, hipMemcpyDeviceToHost, s));
+      BM25_HIP(hipStreamSynchronize(s));
+    }
+    const int64_t h_max = kDenseBytes / (idx->n_pad * sb);
+    std::vector<std::pair<int32_t, int32_t>> cand;  // (-df, token): most frequent first
+    cand.reserve(n_cand);
+    for (uint32_t i = 0; i < n_cand; ++i) cand.emplace_back(-cd[i], ct[i]);
+    std::sort(cand.begin(), cand.end());
+    if ((int64_t)cand.size() > h_max) cand.resize((size_t)std::max<int64_t>(h_max, 0));
+    std::vector<int32_t> toks;
+    for (auto& c : cand) toks.push_back(c.second);
+    std::sort(toks.begin(), toks.end());
+    idx->n_dense = (int64_t)toks.size();
+    // rank of each row by document frequency, for grouping queries that share frequent rows
+    std::vector<int32_t> rank(std::max<size_t>(toks.size(), 1), 0);
+    for (size_t r = 0; r < cand.size(); ++r)
+      rank[(size_t)(std::lower_bound(toks.begin(), toks.end(), cand[r].second) - toks.begin())] =
+          (int32_t)r;
+    BM25_ALLOC(idx->dense_rank, rank.size() * 4);
+    BM25_HIP(hipMemcpyAsync(idx->dense_rank.ptr, rank.data(), rank.size() * 4,
+                            hipMemcpyHostToDevice, s));
+    BM25_ALLOC(idx->dense_id, (size_t)V * 4);
+    hipLaunchKernelGGL(k_fill_i32, dim3(grid_for(V, 256)), dim3(256), 0, s,
+                       idx->dense_id.as<int32_t>(), (int64_t)V, -1);
+    BM25_HIP(hipGetLastError());
+    if (!toks.empty()) {
+      // the chosen tokens go through the (now free) candidate list
+      BM25_HIP(hipMemcpyAsync(cand_tok, toks.data(), toks.size() * 4, hipMemcpyHostToDevice, s));
+      hipLaunchKernelGGL(k_set_dense_ids, dim3(grid_for((int64_t)toks.size(), 256)), dim3(256),
+                         0, s, cand_tok, (int32_t)toks.size(), idx->dense_id.as<int32_t>());
+      BM25_HIP(hipGetLastError());
+    }
+    // the host vectors above are read by the copies in flight: wait before they go
+    BM25_HIP(hipStreamSynchronize(s));
+  }
+  const size_t dbytes = (size_t)std::max<int64_t>(1, idx->n_dense) * idx->n_pad * sb;
+  BM25_ALLOC(idx->dense, dbytes);
+  if (idx->n_dense > 0) BM25_HIP(hipMemsetAsync(idx->dense.ptr, 0, dbytes, s));
+  idx->n_long = n_long;
+  idx->n_blocks = (N + kSkipBlock - 1) / kSkipBlock;
+  BM25_ALLOC(idx->skip, (size_t)std::max<int64_t>(1, (int64_t)n_long * (idx->n_blocks + 1)) * 4);
+
+  // 7. per-pair scores, with the skip table of long rows and the dense rows
   BM25_ALLOC(idx->indices, (size_t)std::max<int64_t>(nnz, 1) * 4);
   BM25_ALLOC(idx->tf, (size_t)std::max<int64_t>(nnz, 1) * 4);
-  BM25_ALLOC(idx->data, (size_t)std::max<int64_t>(nnz, 1) * store_bytes(P.store_dtype));
+  BM25_ALLOC(idx->data, (size_t)std::max<int64_t>(nnz, 1) * sb);
   ScoreParams sp;
   sp.k1 = (float)P.k1;
   sp.b = (float)P.b;
@@ -776,95 +868,47 @@ extern "C" int bm25_index_build(const int32_t* token_ids, int64_t n_tokens,
   sp.inv_lavg = (float)(1.0 / idx->l_avg);
   sp.delta_log0 = (P.variant == BM25_TFLDP) ? (float)(1.0 + std::log(P.delta)) : 1.0f;
   sp.variant = P.variant;
+  SkipOut sko;
+  sko.long_id = idx->long_id.as<int32_t>();
+  sko.indptr = idx->indptr.as<int64_t>();
+  sko.nblocks = idx->n_blocks;
+  sko.skip = idx->skip.as<uint32_t>();
   if (nnz > 0) {
     const unsigned g = grid_for(nnz, 256);
     switch (P.store_dtype) {
-      case BM25_F32:
+      case BM25_F32: {
+        DenseOut<float> dno{idx->dense_id.as<int32_t>(), idx->n_pad, idx->dense.as<float>()};
         hipLaunchKernelGGL(k_score<F32>, dim3(g), dim3(256), 0, s, uniq, starts.as<uint32_t>(),
                            nnz, idx->doclen.as<int32_t>(), idx->idf.as<double>(), sp, kl,
                            idx->indices.as<int32_t>(), idx->tf.as<int32_t>(),
-                           idx->data.as<float>(), range_dev);
+                           idx->data.as<float>(), range_dev, sko, dno);
         break;
-      case BM25_F16:
+      }
+      case BM25_F16: {
+        DenseOut<__half> dno{idx->dense_id.as<int32_t>(), idx->n_pad, idx->dense.as<__half>()};
         hipLaunchKernelGGL(k_score<F16>, dim3(g), dim3(256), 0, s, uniq, starts.as<uint32_t>(),
                            nnz, idx->doclen.as<int32_t>(), idx->idf.as<double>(), sp, kl,
                            idx->indices.as<int32_t>(), idx->tf.as<int32_t>(),
-                           idx->data.as<__half>(), range_dev);
+                           idx->data.as<__half>(), range_dev, sko, dno);
         break;
-      default:
+      }
+      default: {
+        DenseOut<uint16_t> dno{idx->dense_id.as<int32_t>(), idx->n_pad,
+                               idx->dense.as<uint16_t>()};
         hipLaunchKernelGGL(k_score<BF16>, dim3(g), dim3(256), 0, s, uniq, starts.as<uint32_t>(),
                            nnz, idx->doclen.as<int32_t>(), idx->idf.as<double>(), sp, kl,
                            idx->indices.as<int32_t>(), idx->tf.as<int32_t>(),
-                           idx->data.as<uint16_t>(), range_dev);
+                           idx->data.as<uint16_t>(), range_dev, sko, dno);
+      }
     }
     BM25_HIP(hipGetLastError());
   }
-
-  // 7. skip table of long rows
-  uint32_t n_long = 0;
   unsigned long long range_h[3] = {0, 0, 0};
-  BM25_HIP(hipMemcpyAsync(&n_long, total.as<uint32_t>() + 1, 4, hipMemcpyDeviceToHost, s));
   BM25_HIP(hipMemcpyAsync(range_h, range_dev, sizeof(range_h), hipMemcpyDeviceToHost, s));
   BM25_HIP(hipStreamSynchronize(s));
   idx->range_subnormal = (int64_t)range_h[0];
   idx->range_to_zero = (int64_t)range_h[1];
   idx->range_overflow = (int64_t)range_h[2];
-  idx->n_long = n_long;
-  idx->n_blocks = (N + kSkipBlock - 1) / kSkipBlock;
-  BM25_ALLOC(idx->skip, (size_t)std::max<int64_t>(1, (int64_t)n_long * (idx->n_blocks + 1)) * 4);
-  if (n_long > 0) {
-    hipLaunchKernelGGL(k_skip, dim3(grid_for(nnz, 256)), dim3(256), 0, s, uniq, nnz, kl,
-                       idx->indices.as<int32_t>(), idx->indptr.as<int64_t>(),
-                       idx->long_id.as<int32_t>(), idx->n_blocks, idx->skip.as<uint32_t>());
-    BM25_HIP(hipGetLastError());
-  }
-  // 8. dense rows of the most frequent tokens
-  {
-    std::vector<int32_t> df_h((size_t)V);
-    BM25_HIP(hipMemcpyAsync(df_h.data(), idx->df.ptr, (size_t)V * 4, hipMemcpyDeviceToHost, s));
-    BM25_HIP(hipStreamSynchronize(s));
-    const int64_t sb = (int64_t)store_bytes(P.store_dtype);
-    idx->n_pad = ((N + kDensePad - 1) / kDensePad) * kDensePad;
-    const int64_t h_max = kDenseBytes / (idx->n_pad * sb);
-    const int64_t min_df = std::max<int64_t>(2, (N + kDenseFraction - 1) / kDenseFraction);
-    std::vector<std::pair<int32_t, int32_t>> cand;  // (-df, token): most frequent first
-    for (int32_t t = 0; t < V; ++t)
-      if (df_h[t] >= min_df) cand.emplace_back(-df_h[t], t);
-    std::sort(cand.begin(), cand.end());
-    if ((int64_t)cand.size() > h_max) cand.resize((size_t)std::max<int64_t>(h_max, 0));
-    std::vector<int32_t> did((size_t)V, -1);
-    // rows in token order, so that the layout does not depend on tie order
-    std::vector<int32_t> toks;
-    for (auto& c : cand) toks.push_back(c.second);
-    std::sort(toks.begin(), toks.end());
-    for (size_t h = 0; h < toks.size(); ++h) did[toks[h]] = (int32_t)h;
-    idx->n_dense = (int64_t)toks.size();
-    // rank of each row by document frequency, for grouping queries that share frequent rows
-    std::vector<int32_t> rank(std::max<size_t>(toks.size(), 1), 0);
-    for (size_t r = 0; r < cand.size(); ++r) rank[(size_t)did[cand[r].second]] = (int32_t)r;
-    BM25_ALLOC(idx->dense_rank, rank.size() * 4);
-    BM25_HIP(hipMemcpyAsync(idx->dense_rank.ptr, rank.data(), rank.size() * 4,
-                            hipMemcpyHostToDevice, s));
-    BM25_ALLOC(idx->dense_id, (size_t)V * 4);
-    BM25_HIP(hipMemcpyAsync(idx->dense_id.ptr, did.data(), (size_t)V * 4, hipMemcpyHostToDevice,
-                            s));
-    const size_t dbytes = (size_t)std::max<int64_t>(1, idx->n_dense) * idx->n_pad * sb;
-    BM25_ALLOC(idx->dense, dbytes);
-    if (idx->n_dense > 0) {
-      BM25_HIP(hipMemsetAsync(idx->dense.ptr, 0, dbytes, s));
-      const unsigned g = grid_for(nnz, 256);
-      if (sb == 4)
-        hipLaunchKernelGGL(k_dense_scatter<uint32_t>, dim3(g), dim3(256), 0, s, uniq, nnz, kl,
-                           idx->dense_id.as<int32_t>(), idx->data.as<uint32_t>(), idx->n_pad,
-                           idx->dense.as<uint32_t>());
-      else
-        hipLaunchKernelGGL(k_dense_scatter<uint16_t>, dim3(g), dim3(256), 0, s, uniq, nnz, kl,
-                           idx->dense_id.as<int32_t>(), idx->data.as<uint16_t>(), idx->n_pad,
-                           idx->dense.as<uint16_t>());
-      BM25_HIP(hipGetLastError());
-    }
-    BM25_HIP(hipStreamSynchronize(s));
-  }
 #undef BM25_ALLOC
   idx->alloc.stream = nullptr;
   *out = idx.release();
