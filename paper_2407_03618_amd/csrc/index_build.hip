@@ -194,9 +194,13 @@ __device__ __forceinline__ uint64_t wave_sum_u64(uint64_t v) {
   return v;
 }
 
-__global__ __launch_bounds__(256) void k_validate(const int32_t* __restrict__ tok, int64_t T,
-                                                  const int64_t* __restrict__ off, int64_t N,
-                                                  int32_t V, int32_t* __restrict__ doclen,
+// Positions per entry of the granule table: gran_doc[g] = the document holding position
+// g * kGranule (documents of valid offsets only).
+constexpr int64_t kGranule = 1024;
+
+__global__ __launch_bounds__(256) void k_validate(int64_t T, const int64_t* __restrict__ off,
+                                                  int64_t N, int32_t* __restrict__ doclen,
+                                                  int32_t* __restrict__ gran_doc,
                                                   BuildStatus* st) {
   const int64_t gid = (int64_t)blockIdx.x * blockDim.x + threadIdx.x;
   const int64_t stride = (int64_t)gridDim.x * blockDim.x;
@@ -212,12 +216,11 @@ __global__ __launch_bounds__(256) void k_validate(const int32_t* __restrict__ to
     doclen[d] = lc;
     mx = mx > (unsigned)lc ? mx : (unsigned)lc;
     local += (uint64_t)(len > 0 ? len : 0);
+    if (lo >= 0 && hi <= T && lo < hi)
+      for (int64_t g = (lo + kGranule - 1) / kGranule; g * kGranule < hi; ++g)
+        gran_doc[g] = (int32_t)d;
   }
   if (gid == 0 && (off[0] != 0 || off[N] != T)) flags |= 1u;
-  for (int64_t p = gid; p < T; p += stride) {
-    const int32_t t = tok[p];
-    if (t < 0 || t >= V) flags |= 2u;
-  }
   local = wave_sum_u64(local);
   if (lane() == 0 && local) atomicAdd(&st->sum_len, (unsigned long long)local);
 #pragma unroll
@@ -227,20 +230,6 @@ __global__ __launch_bounds__(256) void k_validate(const int32_t* __restrict__ to
   }
   if (lane() == 0 && mx) atomicMax(&st->max_len, mx);
   if (flags) atomicOr(&st->flags, flags);
-}
-
-// One key per position (KeyLayout).
-__global__ __launch_bounds__(256) void k_make_keys(const int32_t* __restrict__ tok,
-                                                   const int64_t* __restrict__ off, int64_t N,
-                                                   KeyLayout L, uint64_t* __restrict__ keys) {
-  const int64_t nwaves = (int64_t)gridDim.x * (blockDim.x / 64);
-  for (int64_t d = ((int64_t)blockIdx.x * blockDim.x + threadIdx.x) / 64; d < N; d += nwaves) {
-    const int64_t lo = off[d], hi = off[d + 1];
-    const uint64_t dl = ((uint64_t)(uint32_t)d << L.doc_shift) |
-                        (L.len_bits > 0 ? (uint64_t)(hi - lo) : 0ull);
-    for (int64_t p = lo + lane(); p < hi; p += 64)
-      keys[p] = ((uint64_t)(uint32_t)tok[p] << L.tok_shift) | dl;
-  }
 }
 
 // Stable LSD radix sort by digits of the token (at most 8 bits each). A block owns
@@ -351,6 +340,84 @@ __global__ __launch_bounds__(256) void k_radix_scatter(const uint64_t* __restric
     const uint32_t d = (uint32_t)(k >> shift) & mask;
     out[(int64_t)gstart[d] + (i - (int64_t)dstart[d])] = k;
   }
+}
+
+// One key per position (KeyLayout), with the histogram of the first radix pass (digit `mask0`
+// of the token) for the same blocks the radix passes use, and the token range check (flag 2).
+// The offsets are valid when this runs. Each wave walks its kRadixWaveItems positions 64 at a time
+// and finds each position's document with a binary search over a window of 64 document starts
+// held one per lane (s_i = off[base + 1 + i]): the document of p is base + #{i : s_i <= p}. A
+// window serves until a round's last position lies past it; a lane whose count is 64 (more than
+// 64 documents start within one round, which takes empty documents) searches further windows.
+__global__ __launch_bounds__(256) void k_keys_hist(const int32_t* __restrict__ tok, int64_t T,
+                                                   const int64_t* __restrict__ off, int64_t N,
+                                                   int32_t V, const int32_t* __restrict__ doclen,
+                                                   const int32_t* __restrict__ gran_doc,
+                                                   KeyLayout L, uint32_t mask0,
+                                                   uint64_t* __restrict__ keys,
+                                                   uint32_t* __restrict__ hist, int64_t nblk,
+                                                   BuildStatus* st) {
+  __shared__ uint32_t h[kRadixBuckets];
+  h[threadIdx.x] = 0;
+  __syncthreads();
+  const int w = threadIdx.x >> 6;
+  const int l = lane();
+  const int64_t q0 = (int64_t)blockIdx.x * kRadixBlockItems + (int64_t)w * kRadixWaveItems;
+  unsigned flags = 0;
+  if (q0 < T) {
+    // window of document starts: lane i holds off[base + 1 + i] (UINT32_MAX past the last)
+    auto window = [&](int64_t b) -> uint32_t {
+      const int64_t i = b + 1 + l;
+      return (i <= N) ? (uint32_t)off[i] : UINT32_MAX;
+    };
+    // #{i < 64 : s_i <= p} for ascending s_i held by the lanes. Every lane runs the search (a
+    // lane permute reads 0 from an inactive lane), so the call must be made by the whole wave.
+    auto count_le = [&](uint32_t sv, uint32_t p) -> int {
+      int pos = 0;
+#pragma unroll
+      for (int step = 32; step >= 1; step >>= 1) {
+        const uint32_t v = bperm(sv, pos + step - 1);
+        pos += (v <= p) ? step : 0;
+      }
+      return (readlane(sv, 63) <= p) ? 64 : pos;
+    };
+    int64_t base = gran_doc[q0 / kGranule];
+    uint32_t sv = window(base);
+    int64_t dcur = base;
+    for (int r = 0; r < kRadixRounds; ++r) {
+      const int64_t p0 = q0 + r * 64;
+      if (p0 >= T) break;
+      const int64_t plast = (p0 + 63 < T) ? p0 + 63 : T - 1;
+      if (readlane(sv, 63) <= (uint32_t)plast) {
+        base = dcur;
+        sv = window(base);
+      }
+      const int64_t p = p0 + l;
+      const bool valid = p < T;
+      int cnt = count_le(sv, (uint32_t)p);
+      int64_t doc = base + cnt;
+      uint64_t more = ballot(valid && cnt == 64);
+      for (int64_t b2 = base + 64; more != 0; b2 += 64) {
+        const uint32_t s2 = window(b2);
+        const int c2 = count_le(s2, (uint32_t)p);
+        if ((more >> l) & 1ull) doc = b2 + c2;
+        more &= ballot(c2 == 64);
+      }
+      const int32_t t = valid ? tok[p] : 0;
+      if (valid && (t < 0 || t >= V)) flags |= 2u;
+      if (valid) {
+        const uint64_t len = (L.len_bits > 0) ? (uint64_t)(uint32_t)doclen[doc] : 0ull;
+        keys[p] = ((uint64_t)(uint32_t)t << L.tok_shift) | ((uint64_t)doc << L.doc_shift) | len;
+      }
+      const uint32_t d = (uint32_t)t & mask0;
+      const uint64_t peers = match_digit8(d) & ballot(valid);
+      if (valid && __builtin_ctzll(peers) == l) atomicAdd(&h[d], (uint32_t)__popcll(peers));
+      dcur = (int64_t)readlane((uint32_t)doc, 63);
+    }
+  }
+  if (flags) atomicOr(&st->flags, flags);
+  __syncthreads();
+  hist[(int64_t)threadIdx.x * nblk + blockIdx.x] = h[threadIdx.x];
 }
 
 // Run-length encoding of equal keys. Each wave owns kRleWaveItems consecutive keys.
@@ -671,18 +738,20 @@ extern "C" int bm25_index_build(const int32_t* token_ids, int64_t n_tokens,
                        (long long)(bytes), hipGetErrorString(e_));                      \
   } while (0)
 
-  // 1. validation, |D|, sum |D|
+  // 1. validation of the offsets, |D|, sum |D|, longest document, granule table (the token ids
+  //    are checked with the keys, step 2)
   DevBuf st(al);
   BM25_ALLOC(st, sizeof(BuildStatus) + 4 * sizeof(unsigned long long));
   BM25_HIP(hipMemsetAsync(st.ptr, 0, sizeof(BuildStatus) + 4 * sizeof(unsigned long long), s));
   unsigned long long* range_dev = reinterpret_cast<unsigned long long*>(st.as<uint8_t>() +
                                                                          sizeof(BuildStatus));
   BM25_ALLOC(idx->doclen, (size_t)N * 4);
+  DevBuf gran(al);
+  BM25_ALLOC(gran, (size_t)((T + kGranule - 1) / kGranule) * 4);
   {
-    int64_t work = std::max(N, T);
-    unsigned g = (unsigned)std::min<int64_t>(grid_for(work, 256), 8192);
-    hipLaunchKernelGGL(k_validate, dim3(g), dim3(256), 0, s, token_ids, T, doc_offsets, N, V,
-                       idx->doclen.as<int32_t>(), st.as<BuildStatus>());
+    unsigned g = (unsigned)std::min<int64_t>(grid_for(N, 256), 8192);
+    hipLaunchKernelGGL(k_validate, dim3(g), dim3(256), 0, s, T, doc_offsets, N,
+                       idx->doclen.as<int32_t>(), gran.as<int32_t>(), st.as<BuildStatus>());
     BM25_HIP(hipGetLastError());
   }
   BuildStatus hst{};
@@ -690,13 +759,17 @@ extern "C" int bm25_index_build(const int32_t* token_ids, int64_t n_tokens,
   BM25_HIP(hipStreamSynchronize(s));
   if (hst.flags & 1u) return set_error(BM25_E_RANGE, "document offsets are malformed");
   if (hst.flags & 4u) return set_error(BM25_E_RANGE, "a document holds more than 2^31-1 tokens");
-  if (hst.flags & 2u) return set_error(BM25_E_RANGE, "a token id lies outside [0, vocab_size)");
   if (hst.sum_len == 0) return set_error(BM25_E_INVAL, "sum of |D| is 0: L_avg is undefined");
   idx->sum_len = (int64_t)hst.sum_len;
   idx->l_avg = (double)idx->sum_len / (double)N;
 
-  // 2. keys
+  // 2. keys with the first radix histogram and the token range check
   const int tbits = bits_needed((uint32_t)(V - 1));
+  const int passes = (tbits + 7) / 8;
+  const int dbits = passes > 0 ? (tbits + passes - 1) / passes : 0;  // digit width, <= 8
+  const uint32_t dmask = (1u << dbits) - 1u;
+  const int64_t nblk = (T + kRadixBlockItems - 1) / kRadixBlockItems;
+  const int64_t hn = nblk * kRadixBuckets;
   KeyLayout kl;
   {
     const int dbits_doc = std::max(1, bits_needed((uint32_t)(N - 1)));
@@ -707,21 +780,17 @@ extern "C" int bm25_index_build(const int32_t* token_ids, int64_t n_tokens,
     kl.doc_mask = (1ull << dbits_doc) - 1;
     kl.tok_shift = kl.len_bits + dbits_doc;
   }
-  DevBuf ka(al), kb(al);
+  DevBuf ka(al), kb(al), hist(al), tmp(al);
   BM25_ALLOC(ka, (size_t)T * 8);
   BM25_ALLOC(kb, (size_t)T * 8);
-  hipLaunchKernelGGL(k_make_keys, dim3((unsigned)std::min<int64_t>(grid_for(N * 64, 256), 65536)),
-                     dim3(256), 0, s, token_ids, doc_offsets, N, kl, ka.as<uint64_t>());
+  BM25_ALLOC(hist, (size_t)hn * 4);
+  hipLaunchKernelGGL(k_keys_hist, dim3((unsigned)nblk), dim3(256), 0, s, token_ids, T,
+                     doc_offsets, N, V, idx->doclen.as<int32_t>(), gran.as<int32_t>(), kl, dmask,
+                     ka.as<uint64_t>(), hist.as<uint32_t>(), nblk, st.as<BuildStatus>());
   BM25_HIP(hipGetLastError());
 
-  // 3. stable LSD radix sort by token digits
-  const int passes = (tbits + 7) / 8;
-  const int dbits = passes > 0 ? (tbits + passes - 1) / passes : 0;  // digit width, <= 8
-  const uint32_t dmask = (1u << dbits) - 1u;
-  const int64_t nblk = (T + kRadixBlockItems - 1) / kRadixBlockItems;
-  const int64_t hn = nblk * kRadixBuckets;
-  DevBuf hist(al), tmp(al);
-  BM25_ALLOC(hist, (size_t)hn * 4);
+  // 3. stable LSD radix sort by token digits (out-of-range ids, reported below, are sorted by
+  //    their masked digits and never index anything)
   const int64_t nrb = (T + kRleBlockItems - 1) / kRleBlockItems;
   BM25_ALLOC(tmp, (size_t)std::max({scan_tmp_elems(hn), scan_tmp_elems(T), scan_tmp_elems(V),
                                     scan_tmp_elems(nrb * 4)}) * 8 + 64);
@@ -729,9 +798,11 @@ extern "C" int bm25_index_build(const int32_t* token_ids, int64_t n_tokens,
   uint64_t* dst = kb.as<uint64_t>();
   for (int pass = 0; pass < passes; ++pass) {
     const int shift = kl.tok_shift + dbits * pass;
-    hipLaunchKernelGGL(k_radix_hist, dim3((unsigned)nblk), dim3(256), 0, s, src, T, shift, dmask,
-                       hist.as<uint32_t>(), nblk);
-    BM25_HIP(hipGetLastError());
+    if (pass > 0) {  // the first pass's histogram came with the keys
+      hipLaunchKernelGGL(k_radix_hist, dim3((unsigned)nblk), dim3(256), 0, s, src, T, shift,
+                         dmask, hist.as<uint32_t>(), nblk);
+      BM25_HIP(hipGetLastError());
+    }
     BM25_HIP(scan_exclusive<uint32_t>(hist.as<uint32_t>(), hist.as<uint32_t>(), hn,
                                       tmp.as<uint32_t>(), nullptr, s));
     hipLaunchKernelGGL(k_radix_scatter, dim3((unsigned)nblk), dim3(256), 0, s, src, dst, T, shift,
@@ -758,7 +829,9 @@ extern "C" int bm25_index_build(const int32_t* token_ids, int64_t n_tokens,
   BM25_HIP(hipGetLastError());
   uint32_t nnz32 = 0;
   BM25_HIP(hipMemcpyAsync(&nnz32, total.ptr, 4, hipMemcpyDeviceToHost, s));
+  BM25_HIP(hipMemcpyAsync(&hst, st.ptr, sizeof(hst), hipMemcpyDeviceToHost, s));
   BM25_HIP(hipStreamSynchronize(s));
+  if (hst.flags & 2u) return set_error(BM25_E_RANGE, "a token id lies outside [0, vocab_size)");
   const int64_t nnz = nnz32;
   idx->nnz = nnz;
   hipLaunchKernelGGL(k_set_u32, dim3(1), dim3(1), 0, s, starts.as<uint32_t>() + nnz, (uint32_t)T);

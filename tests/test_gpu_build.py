@@ -80,6 +80,32 @@ def test_empty_documents_and_single_token_vocab():
     _compare(idx, ref, "f32", "single token")
 
 
+@pytest.mark.parametrize("shape", ["empty_runs", "one_token_docs", "long_docs"])
+def test_document_layouts(shape):
+    """Documents that are mostly empty (hundreds of document starts inside one 64-position run),
+    one token long, or thousands of tokens long, so that the build's position-to-document search
+    takes every path; a negative token id is still reported."""
+    from workloads.synth import Corpus
+    rng = np.random.default_rng({"empty_runs": 1, "one_token_docs": 2, "long_docs": 3}[shape])
+    if shape == "empty_runs":
+        lens = np.where(rng.random(30_000) < 0.97, 0, rng.integers(1, 40, 30_000))
+        lens[:500] = 0
+        lens[-700:] = 0
+    elif shape == "one_token_docs":
+        lens = rng.integers(0, 3, 50_000)
+    else:
+        lens = rng.integers(1500, 9000, 40)
+    off = np.zeros(lens.size + 1, np.int64)
+    off[1:] = np.cumsum(lens)
+    V = 3000
+    tokens = np.minimum(rng.zipf(1.3, int(off[-1])) - 1, V - 1).astype(np.int32)
+    c = Corpus(tokens, off, V)
+    ref = eager.build_index(tokens, off, V)
+    idx = _build(c, dtype="f16")
+    _compare(idx, ref, "f16", shape)
+    idx.free()
+
+
 def test_build_errors():
     from paper_2407_03618_amd import BM25Error, Index
     import torch
@@ -94,6 +120,9 @@ def test_build_errors():
     assert e.value.code == -2
     with pytest.raises(BM25Error) as e:
         Index(tok, _dev(np.array([1, 2, 3], np.int64)), 3)
+    assert e.value.code == -2
+    with pytest.raises(BM25Error) as e:
+        Index(_dev(np.array([0, -1, 2], np.int32)), off.clone(), 3)
     assert e.value.code == -2
     with pytest.raises(BM25Error) as e:
         Index(tok, off.clone(), 3, b=1.5)
