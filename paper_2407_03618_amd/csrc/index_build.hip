@@ -264,10 +264,16 @@ __global__ __launch_bounds__(256) void k_radix_hist(const uint64_t* __restrict__
   const int w = threadIdx.x >> 6;
   const int l = lane();
   const int64_t base = (int64_t)blockIdx.x * kRadixBlockItems + (int64_t)w * kRadixWaveItems;
+  uint64_t key[kRadixRounds];  // all loads in flight before the counting
+#pragma unroll
   for (int r = 0; r < kRadixRounds; ++r) {
     const int64_t i = base + r * 64 + l;
-    const bool valid = i < n;
-    const uint32_t d = valid ? (uint32_t)(keys[i] >> shift) & mask : 0u;
+    key[r] = (i < n) ? keys[i] : 0ull;
+  }
+#pragma unroll
+  for (int r = 0; r < kRadixRounds; ++r) {
+    const bool valid = base + r * 64 + l < n;
+    const uint32_t d = (uint32_t)(key[r] >> shift) & mask;
     const uint64_t peers = match_digit8(d) & ballot(valid);
     if (valid && __builtin_ctzll(peers) == l) atomicAdd(&h[d], (uint32_t)__popcll(peers));
   }
@@ -438,40 +444,72 @@ __global__ __launch_bounds__(256) void k_rle_count(const uint64_t* __restrict__ 
   if (l == 0) counts[(int64_t)blockIdx.x * 4 + w] = c;
 }
 
+// Write side: the head of every run (a key that differs from the one before it) at position i
+// becomes stored pair j, its rank among the heads: uniq[j] = key and tf[j] = the run length (the
+// next head's position - i; the last run of a wave may end in the next wave's range, which the
+// wave then reads until a different key). Where the token changes at a head, indptr[t] = j for the
+// tokens t after the previous head's token up to this one; the wave holding the last position
+// sets indptr[t] = nnz above the last token. Token ids are clamped to V here, so that ids out of
+// range (reported at the next host sync) never index past indptr.
 __global__ __launch_bounds__(256) void k_rle_write(const uint64_t* __restrict__ keys, int64_t n,
                                                    const uint32_t* __restrict__ bases,
+                                                   KeyLayout L, int32_t V,
                                                    uint64_t* __restrict__ uniq,
-                                                   uint32_t* __restrict__ starts) {
+                                                   int32_t* __restrict__ tf,
+                                                   int64_t* __restrict__ indptr) {
   const int w = threadIdx.x >> 6;
   const int l = lane();
   const int64_t base = (int64_t)blockIdx.x * kRleBlockItems + (int64_t)w * kRleWaveItems;
+  if (base >= n) return;
   uint32_t run = bases[(int64_t)blockIdx.x * 4 + w];
   const uint64_t lt = lanemask_lt();
+  auto tok_of = [&](uint64_t k) -> int64_t {
+    const uint32_t t = key_token(k, L);
+    return t < (uint32_t)V ? (int64_t)t : (int64_t)V;
+  };
+  int64_t pend_i = -1;  // last head so far, whose run is still open, and its pair
+  uint32_t pend_j = 0;
   for (int r = 0; r < kRleWaveItems / 64; ++r) {
-    const int64_t i = base + r * 64 + l;
-    const uint64_t key = i < n ? keys[i] : 0ull;
-    const bool head = i < n && (i == 0 || key != keys[i - 1]);
+    const int64_t i0 = base + r * 64;
+    if (i0 >= n) break;
+    const int64_t i = i0 + l;
+    const bool valid = i < n;
+    const uint64_t key = valid ? keys[i] : 0ull;
+    const uint64_t prev = (valid && i > 0) ? keys[i - 1] : 0ull;
+    const bool head = valid && (i == 0 || key != prev);
     const uint64_t m = ballot(head);
     if (head) {
       const uint32_t j = run + (uint32_t)__popcll(m & lt);
       uniq[j] = key;
-      starts[j] = (uint32_t)i;
+      const uint64_t after = (l == 63) ? 0ull : (m >> (l + 1));
+      if (after) tf[j] = (int32_t)(__builtin_ctzll(after) + 1);
+      const int64_t t = tok_of(key);
+      const int64_t pt = (i == 0) ? -1 : tok_of(prev);
+      for (int64_t u = pt + 1; u <= t; ++u) indptr[u] = j;
+    }
+    if (m) {
+      if (pend_i >= 0 && l == 0) tf[pend_j] = (int32_t)(i0 + __builtin_ctzll(m) - pend_i);
+      pend_i = i0 + (63 - __builtin_clzll(m));
+      pend_j = run + (uint32_t)__popcll(m) - 1;
     }
     run += (uint32_t)__popcll(m);
   }
-}
-
-__global__ void k_set_u32(uint32_t* p, uint32_t v) { *p = v; }
-
-// indptr[t] = first stored pair whose token is >= t, for t in [0, V].
-__global__ __launch_bounds__(256) void k_indptr(const uint64_t* __restrict__ uniq, int64_t nnz,
-                                                int32_t V, KeyLayout L,
-                                                int64_t* __restrict__ indptr) {
-  const int64_t j = (int64_t)blockIdx.x * blockDim.x + threadIdx.x;
-  if (j > nnz) return;
-  const int64_t cur = (j < nnz) ? (int64_t)key_token(uniq[j], L) : (int64_t)V;
-  const int64_t prev = (j > 0) ? (int64_t)key_token(uniq[j - 1], L) : -1;
-  for (int64_t t = prev + 1; t <= cur; ++t) indptr[t] = j;
+  if (pend_i >= 0) {
+    const uint64_t pk = keys[pend_i];
+    int64_t end = n;
+    for (int64_t q = base + kRleWaveItems; q < n; q += 64) {
+      const uint64_t dm = ballot(q + l < n && keys[q + l] != pk);
+      if (dm) {
+        end = q + __builtin_ctzll(dm);
+        break;
+      }
+    }
+    if (l == 0) tf[pend_j] = (int32_t)(end - pend_i);
+  }
+  if (n - 1 < base + kRleWaveItems && l == 0) {
+    const int64_t t_last = tok_of(keys[n - 1]);
+    for (int64_t u = t_last + 1; u <= (int64_t)V; ++u) indptr[u] = run;
+  }
 }
 
 // IDF(t, C) in FP64 per variant; the Lucene form is the IDF equation of Section 2.
@@ -613,16 +651,15 @@ struct DenseOut {
   T* dense;
 };
 
-// Per stored pair: document id, TF, stored score and its range class; the pair's entries in the
+// Per stored pair: document id, stored score and its range class; the pair's entries in the
 // skip table (long rows) and its value in the dense rows (dense-row tokens).
 template <typename ST>
 __global__ __launch_bounds__(256) void k_score(const uint64_t* __restrict__ uniq,
-                                               const uint32_t* __restrict__ starts, int64_t nnz,
+                                               const int32_t* __restrict__ tf_in, int64_t nnz,
                                                const int32_t* __restrict__ doclen,
                                                const double* __restrict__ idf, ScoreParams p,
                                                KeyLayout L,
                                                int32_t* __restrict__ indices,
-                                               int32_t* __restrict__ tf_out,
                                                typename ST::T* __restrict__ data,
                                                unsigned long long* __restrict__ range,
                                                SkipOut sko, DenseOut<typename ST::T> dno) {
@@ -632,9 +669,8 @@ __global__ __launch_bounds__(256) void k_score(const uint64_t* __restrict__ uniq
     const uint64_t key = uniq[j];
     const uint32_t t = key_token(key, L);
     const uint32_t d = key_doc(key, L);
-    const uint32_t tf = starts[j + 1] - starts[j];
+    const uint32_t tf = (uint32_t)tf_in[j];
     indices[j] = (int32_t)d;
-    tf_out[j] = (int32_t)tf;
     const float w = (float)idf[t];
     const uint32_t len = (L.len_bits > 0) ? (uint32_t)key & L.len_mask : (uint32_t)doclen[d];
     const float x = w * stored_factor((float)tf, (float)len, p);
@@ -821,12 +857,6 @@ extern "C" int bm25_index_build(const int32_t* token_ids, int64_t n_tokens,
   BM25_HIP(hipGetLastError());
   BM25_HIP(scan_exclusive<uint32_t>(counts.as<uint32_t>(), counts.as<uint32_t>(), nrb * 4,
                                     tmp.as<uint32_t>(), total.as<uint32_t>(), s));
-  uint64_t* uniq = dst;  // the other sort buffer
-  DevBuf starts(al);
-  BM25_ALLOC(starts, ((size_t)T + 1) * 4);
-  hipLaunchKernelGGL(k_rle_write, dim3((unsigned)nrb), dim3(256), 0, s, src, T,
-                     counts.as<uint32_t>(), uniq, starts.as<uint32_t>());
-  BM25_HIP(hipGetLastError());
   uint32_t nnz32 = 0;
   BM25_HIP(hipMemcpyAsync(&nnz32, total.ptr, 4, hipMemcpyDeviceToHost, s));
   BM25_HIP(hipMemcpyAsync(&hst, st.ptr, sizeof(hst), hipMemcpyDeviceToHost, s));
@@ -834,19 +864,20 @@ extern "C" int bm25_index_build(const int32_t* token_ids, int64_t n_tokens,
   if (hst.flags & 2u) return set_error(BM25_E_RANGE, "a token id lies outside [0, vocab_size)");
   const int64_t nnz = nnz32;
   idx->nnz = nnz;
-  hipLaunchKernelGGL(k_set_u32, dim3(1), dim3(1), 0, s, starts.as<uint32_t>() + nnz, (uint32_t)T);
+  uint64_t* uniq = dst;  // the other sort buffer
+  BM25_ALLOC(idx->tf, (size_t)std::max<int64_t>(nnz, 1) * 4);
+  BM25_ALLOC(idx->indptr, ((size_t)V + 1) * 8);
+  hipLaunchKernelGGL(k_rle_write, dim3((unsigned)nrb), dim3(256), 0, s, src, T,
+                     counts.as<uint32_t>(), kl, V, uniq, idx->tf.as<int32_t>(),
+                     idx->indptr.as<int64_t>());
   BM25_HIP(hipGetLastError());
 
-  // 5. indptr, DF, IDF, S_theta, long rows, dense-row candidates
-  BM25_ALLOC(idx->indptr, ((size_t)V + 1) * 8);
+  // 5. DF, IDF, S_theta, long rows, dense-row candidates
   BM25_ALLOC(idx->df, (size_t)V * 4);
   BM25_ALLOC(idx->idf, (size_t)V * 8);
   BM25_ALLOC(idx->theta, (size_t)V * 8);
   BM25_ALLOC(idx->theta32, (size_t)V * 4);
   BM25_ALLOC(idx->long_id, (size_t)V * 4);
-  hipLaunchKernelGGL(k_indptr, dim3(grid_for(nnz + 1, 256)), dim3(256), 0, s, uniq, nnz, V, kl,
-                     idx->indptr.as<int64_t>());
-  BM25_HIP(hipGetLastError());
   const int64_t min_dense_df = std::max<int64_t>(2, (N + kDenseFraction - 1) / kDenseFraction);
   DevBuf is_long(al), long_excl(al), is_dense(al), dense_excl(al);
   BM25_ALLOC(is_long, (size_t)V * 4);
@@ -932,7 +963,6 @@ extern "C" int bm25_index_build(const int32_t* token_ids, int64_t n_tokens,
 
   // 7. per-pair scores, with the skip table of long rows and the dense rows
   BM25_ALLOC(idx->indices, (size_t)std::max<int64_t>(nnz, 1) * 4);
-  BM25_ALLOC(idx->tf, (size_t)std::max<int64_t>(nnz, 1) * 4);
   BM25_ALLOC(idx->data, (size_t)std::max<int64_t>(nnz, 1) * sb);
   ScoreParams sp;
   sp.k1 = (float)P.k1;
@@ -951,27 +981,27 @@ extern "C" int bm25_index_build(const int32_t* token_ids, int64_t n_tokens,
     switch (P.store_dtype) {
       case BM25_F32: {
         DenseOut<float> dno{idx->dense_id.as<int32_t>(), idx->n_pad, idx->dense.as<float>()};
-        hipLaunchKernelGGL(k_score<F32>, dim3(g), dim3(256), 0, s, uniq, starts.as<uint32_t>(),
+        hipLaunchKernelGGL(k_score<F32>, dim3(g), dim3(256), 0, s, uniq, idx->tf.as<int32_t>(),
                            nnz, idx->doclen.as<int32_t>(), idx->idf.as<double>(), sp, kl,
-                           idx->indices.as<int32_t>(), idx->tf.as<int32_t>(),
-                           idx->data.as<float>(), range_dev, sko, dno);
+                           idx->indices.as<int32_t>(), idx->data.as<float>(), range_dev, sko,
+                           dno);
         break;
       }
       case BM25_F16: {
         DenseOut<__half> dno{idx->dense_id.as<int32_t>(), idx->n_pad, idx->dense.as<__half>()};
-        hipLaunchKernelGGL(k_score<F16>, dim3(g), dim3(256), 0, s, uniq, starts.as<uint32_t>(),
+        hipLaunchKernelGGL(k_score<F16>, dim3(g), dim3(256), 0, s, uniq, idx->tf.as<int32_t>(),
                            nnz, idx->doclen.as<int32_t>(), idx->idf.as<double>(), sp, kl,
-                           idx->indices.as<int32_t>(), idx->tf.as<int32_t>(),
-                           idx->data.as<__half>(), range_dev, sko, dno);
+                           idx->indices.as<int32_t>(), idx->data.as<__half>(), range_dev, sko,
+                           dno);
         break;
       }
       default: {
         DenseOut<uint16_t> dno{idx->dense_id.as<int32_t>(), idx->n_pad,
                                idx->dense.as<uint16_t>()};
-        hipLaunchKernelGGL(k_score<BF16>, dim3(g), dim3(256), 0, s, uniq, starts.as<uint32_t>(),
+        hipLaunchKernelGGL(k_score<BF16>, dim3(g), dim3(256), 0, s, uniq, idx->tf.as<int32_t>(),
                            nnz, idx->doclen.as<int32_t>(), idx->idf.as<double>(), sp, kl,
-                           idx->indices.as<int32_t>(), idx->tf.as<int32_t>(),
-                           idx->data.as<uint16_t>(), range_dev, sko, dno);
+                           idx->indices.as<int32_t>(), idx->data.as<uint16_t>(), range_dev, sko,
+                           dno);
       }
     }
     BM25_HIP(hipGetLastError());
