@@ -221,14 +221,28 @@ __global__ __launch_bounds__(256) void k_validate(int64_t T, const int64_t* __re
         gran_doc[g] = (int32_t)d;
   }
   if (gid == 0 && (off[0] != 0 || off[N] != T)) flags |= 1u;
+  // one atomic per block and quantity (same-address atomics from every wave serialize)
+  __shared__ unsigned long long bsum[4];
+  __shared__ unsigned bmax[4];
   local = wave_sum_u64(local);
-  if (lane() == 0 && local) atomicAdd(&st->sum_len, (unsigned long long)local);
 #pragma unroll
   for (int o = 32; o > 0; o >>= 1) {
     const unsigned y = bperm(mx, lane() ^ o);
     mx = mx > y ? mx : y;
   }
-  if (lane() == 0 && mx) atomicMax(&st->max_len, mx);
+  if (lane() == 0) {
+    bsum[threadIdx.x >> 6] = local;
+    bmax[threadIdx.x >> 6] = mx;
+  }
+  __syncthreads();
+  if (threadIdx.x == 0) {
+    const unsigned long long sum = bsum[0] + bsum[1] + bsum[2] + bsum[3];
+    const unsigned m01 = bmax[0] > bmax[1] ? bmax[0] : bmax[1];
+    const unsigned m23 = bmax[2] > bmax[3] ? bmax[2] : bmax[3];
+    const unsigned m = m01 > m23 ? m01 : m23;
+    if (sum) atomicAdd(&st->sum_len, sum);
+    if (m) atomicMax(&st->max_len, m);
+  }
   if (flags) atomicOr(&st->flags, flags);
 }
 
@@ -353,8 +367,10 @@ __global__ __launch_bounds__(256) void k_radix_scatter(const uint64_t* __restric
 // The offsets are valid when this runs. Each wave walks its kRadixWaveItems positions 64 at a time
 // and finds each position's document with a binary search over a window of 64 document starts
 // held one per lane (s_i = off[base + 1 + i]): the document of p is base + #{i : s_i <= p}. A
-// window serves until a round's last position lies past it; a lane whose count is 64 (more than
-// 64 documents start within one round, which takes empty documents) searches further windows.
+// window serves until a round's last position lies past it. A round's first and last positions
+// are searched once for the whole wave; the few documents starting between them decide each
+// lane's document and give its length from the same window. A round in which more than 64
+// documents start (empty documents) has every lane search the window, then further windows.
 __global__ __launch_bounds__(256) void k_keys_hist(const int32_t* __restrict__ tok, int64_t T,
                                                    const int64_t* __restrict__ off, int64_t N,
                                                    int32_t V, const int32_t* __restrict__ doclen,
@@ -387,8 +403,18 @@ __global__ __launch_bounds__(256) void k_keys_hist(const int32_t* __restrict__ t
       }
       return (readlane(sv, 63) <= p) ? 64 : pos;
     };
+    // the same count for a position x held by every lane (a scalar search)
+    auto count_le_u = [&](uint32_t sv, uint32_t x) -> int {
+      if (readlane(sv, 63) <= x) return 64;
+      int pos = 0;
+#pragma unroll
+      for (int step = 32; step >= 1; step >>= 1)
+        if (readlane(sv, pos + step - 1) <= x) pos += step;
+      return pos;
+    };
     int64_t base = gran_doc[q0 / kGranule];
     uint32_t sv = window(base);
+    uint32_t off_base = (uint32_t)off[base];
     int64_t dcur = base;
     for (int r = 0; r < kRadixRounds; ++r) {
       const int64_t p0 = q0 + r * 64;
@@ -397,24 +423,49 @@ __global__ __launch_bounds__(256) void k_keys_hist(const int32_t* __restrict__ t
       if (readlane(sv, 63) <= (uint32_t)plast) {
         base = dcur;
         sv = window(base);
+        off_base = (uint32_t)off[base];
       }
       const int64_t p = p0 + l;
       const bool valid = p < T;
-      int cnt = count_le(sv, (uint32_t)p);
-      int64_t doc = base + cnt;
-      uint64_t more = ballot(valid && cnt == 64);
-      for (int64_t b2 = base + 64; more != 0; b2 += 64) {
-        const uint32_t s2 = window(b2);
-        const int c2 = count_le(s2, (uint32_t)p);
-        if ((more >> l) & 1ull) doc = b2 + c2;
-        more &= ballot(c2 == 64);
-      }
       const int32_t t = valid ? tok[p] : 0;
-      if (valid && (t < 0 || t >= V)) flags |= 2u;
-      if (valid) {
-        const uint64_t len = (L.len_bits > 0) ? (uint64_t)(uint32_t)doclen[doc] : 0ull;
-        keys[p] = ((uint64_t)(uint32_t)t << L.tok_shift) | ((uint64_t)doc << L.doc_shift) | len;
+      int64_t doc;
+      uint32_t len;
+      // documents starting inside this round: window entries [c0, c1)
+      const int c0 = count_le_u(sv, (uint32_t)p0);
+      const int c1 = count_le_u(sv, (uint32_t)plast);
+      if (c1 < 64) {
+        int cnt = c0;
+        uint32_t lo = (c0 > 0) ? readlane(sv, c0 - 1) : off_base;
+        uint32_t hi = readlane(sv, c0);
+        for (int i = c0; i < c1; ++i) {
+          const uint32_t si = readlane(sv, i);
+          const uint32_t sn = readlane(sv, i + 1);
+          if (si <= (uint32_t)p) {
+            ++cnt;
+            lo = si;
+            hi = sn;
+          }
+        }
+        doc = base + cnt;
+        len = hi - lo;
+      } else {
+        // more than 64 documents start inside the round (empty documents): each lane searches
+        // the window, then further windows
+        const int cnt = count_le(sv, (uint32_t)p);
+        doc = base + cnt;
+        uint64_t more = ballot(valid && cnt == 64);
+        for (int64_t b2 = base + 64; more != 0; b2 += 64) {
+          const uint32_t s2 = window(b2);
+          const int cc = count_le(s2, (uint32_t)p);
+          if ((more >> l) & 1ull) doc = b2 + cc;
+          more &= ballot(cc == 64);
+        }
+        len = valid ? (uint32_t)doclen[doc] : 0u;
       }
+      if (valid && (t < 0 || t >= V)) flags |= 2u;
+      if (valid)
+        keys[p] = ((uint64_t)(uint32_t)t << L.tok_shift) | ((uint64_t)doc << L.doc_shift) |
+                  (L.len_bits > 0 ? (uint64_t)len : 0ull);
       const uint32_t d = (uint32_t)t & mask0;
       const uint64_t peers = match_digit8(d) & ballot(valid);
       if (valid && __builtin_ctzll(peers) == l) atomicAdd(&h[d], (uint32_t)__popcll(peers));
@@ -785,7 +836,7 @@ extern "C" int bm25_index_build(const int32_t* token_ids, int64_t n_tokens,
   DevBuf gran(al);
   BM25_ALLOC(gran, (size_t)((T + kGranule - 1) / kGranule) * 4);
   {
-    unsigned g = (unsigned)std::min<int64_t>(grid_for(N, 256), 8192);
+    unsigned g = (unsigned)std::min<int64_t>(grid_for(N, 256), 2048);
     hipLaunchKernelGGL(k_validate, dim3(g), dim3(256), 0, s, T, doc_offsets, N,
                        idx->doclen.as<int32_t>(), gran.as<int32_t>(), st.as<BuildStatus>());
     BM25_HIP(hipGetLastError());
