@@ -155,6 +155,17 @@ static int fit_q_tile(int want, int kpl, int waves, int R) {
 }
 
 // accumulators + entry state (static and one cursor copy) + member copy
+// Largest multiplicity of one dense entry in the batched form: the gather adds 16-bit stored rows
+// on the matrix cores with the multiplicity as a 16-bit operand, exact for integers up to 2^11
+// (FP16) or 2^8 (BF16); FP32 rows are added on the vector units with no limit.
+static int32_t dense_mult_max(const bm25_index* idx) {
+  switch (idx->params.store_dtype) {
+    case BM25_F16: return 2048;
+    case BM25_BF16: return 256;
+    default: return INT32_MAX;
+  }
+}
+
 static int64_t gather_lds(const TileShape& t, int64_t ecap, int64_t pcap) {
   return (int64_t)t.q_tile * t.doc_tile * 4 + ecap * (kEntryStaticBytes + kEntryDynBytes) +
          pcap * 4 + 64;
@@ -627,6 +638,7 @@ int search_batch_impl(bm25_index* idx, const int32_t* q_ids, const int64_t* q_of
     bv.tile_cost = ordered ? reinterpret_cast<float*>(base + L.tile_cost) : nullptr;
     bv.n_queries = n;
     bv.n_tiles = n_tiles;
+    bv.dense_mult_max = dense_mult_max(idx);
 
     hipLaunchKernelGGL(k_plan, dim3(n_tiles), dim3(kPlanThreads), 0, q, ix, bv, W);
     BM25_HIP(hipGetLastError());

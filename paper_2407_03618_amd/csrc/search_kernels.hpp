@@ -82,6 +82,9 @@ struct BatchView {
   float* tile_cost = nullptr;  // [n_tiles]: estimated gather work of each tile, if wanted
   int32_t n_queries;
   int32_t n_tiles;
+  // largest multiplicity of one dense entry (larger ones are split over several entries): the
+  // largest integer up to which the matrix-core operand of the stored type is exact
+  int32_t dense_mult_max = INT32_MAX;
 };
 
 // Relative gather work of a tile, in units of one sparse posting added for one query, used only
@@ -375,10 +378,14 @@ __global__ __launch_bounds__(kPlanThreads) void k_plan(IndexView ix, BatchView b
     bv.members[p0 + m] = (int32_t)(ql | (mult << 16));
   }
 
-  // 3b. dense tokens: one entry per distinct multiplicity, with the mask of its queries
+  // 3b. dense tokens: one entry per distinct multiplicity, with the mask of its queries; a
+  //     multiplicity above bv.dense_mult_max is split over entries of the same row and mask whose
+  //     multiplicities add up to it (at most one entry per query position, so they fit)
   auto is_dense = [&](uint32_t u) {
     return ix.dense_id != nullptr && ix.dense_id[sm.tok[u]] >= 0;
   };
+  const uint32_t mmax = (uint32_t)bv.dense_mult_max;
+  auto pieces = [&](uint32_t mult) { return (mult + mmax - 1) / mmax; };
   for (int u = tid; u < kPlanSort; u += kPlanThreads) {
     uint32_t cnt = 0;
     if ((uint32_t)u < n_tok && is_dense((uint32_t)u)) {
@@ -388,7 +395,7 @@ __global__ __launch_bounds__(kPlanThreads) void k_plan(IndexView ix, BatchView b
         bool seen = false;
         for (uint32_t mm = m0; mm < m; ++mm)
           seen |= (sm.pos_of_member[mm + 1] - sm.pos_of_member[mm]) == mult;
-        cnt += seen ? 0u : 1u;
+        cnt += seen ? 0u : pieces(mult);
       }
     }
     sm.dcnt[u] = cnt;
@@ -409,13 +416,17 @@ __global__ __launch_bounds__(kPlanThreads) void k_plan(IndexView ix, BatchView b
       for (uint32_t mm = m; mm < m1; ++mm)
         if (sm.pos_of_member[mm + 1] - sm.pos_of_member[mm] == mult)
           mask |= 1u << (uint32_t)(sm.key[sm.pos_of_member[mm]] & 31u);
-      DenseEntry de;
-      de.row = ix.dense_id[sm.tok[u]];
-      de.qmask = mask;
-      de.mult = (float)mult;
-      de.token = sm.tok[u];
-      bv.dense_ent[p0 + o] = de;
-      ++o;
+      for (uint32_t rest = mult; rest > 0;) {
+        const uint32_t take = rest < mmax ? rest : mmax;
+        DenseEntry de;
+        de.row = ix.dense_id[sm.tok[u]];
+        de.qmask = mask;
+        de.mult = (float)take;
+        de.token = sm.tok[u];
+        bv.dense_ent[p0 + o] = de;
+        ++o;
+        rest -= take;
+      }
     }
   }
   if (tid == 0) bv.dense_n[tile] = (int32_t)n_dent;
@@ -935,9 +946,135 @@ __device__ __forceinline__ void accumulate_dense_f16(const IndexView& ix, const 
   }
 }
 
+// Dense rows of 16-bit stored scores on the matrix cores. For a tile, the dense-row work is the
+// product (queries x entries) . (entries x documents): A[q][e] = the multiplicity of entry e for
+// query q (0 when q is not a member), B[e][d] = the stored score of entry e's row at document d.
+// v_mfma_f32_4x4x4{f16,bf16_1k} runs 16 blocks of a 4x4x4 product; in block b, lane 4b + i
+// supplies row i of A and lane 4b + j column j of B, and lane 4b + j receives column j of D, one
+// query per register (the layout was checked on the device). So every lane supplies, as A, the
+// multiplicities of query (lane & 3) (+ 4 per query group) for 4 entries, and as B the 4 entries'
+// scores at one of its own documents, and gets back the 4 queries' sums for that document: one
+// instruction per (query group, document of the lane) per 4 entries, with no per-query branch.
+// Products of 16-bit values are exact in FP32, and the sums accumulate in FP32. The planner keeps
+// every entry's multiplicity within the integers the operand type holds exactly (2^11 in FP16,
+// 2^8 in BF16: dense_mult_max), splitting larger ones over several entries.
+constexpr bool kDenseMfma = true;
+
+typedef _Float16 mfma_h4 __attribute__((ext_vector_type(4)));
+typedef short mfma_s4 __attribute__((ext_vector_type(4)));
+typedef float mfma_f4 __attribute__((ext_vector_type(4)));
+typedef uint32_t mfma_u2 __attribute__((ext_vector_type(2)));  // 4 packed 16-bit operands
+
+template <typename ST>
+__device__ __forceinline__ uint32_t mult_bits16(float m) {
+  if constexpr (std::is_same<ST, F16>::value)
+    return (uint32_t)__half_as_ushort(__float2half_rn(m));
+  else
+    return __float_as_uint(m) >> 16;  // exact for the integers this is used for
+}
+
+template <typename ST>
+__device__ __forceinline__ mfma_f4 mfma_4x4x4(mfma_u2 a, mfma_u2 b, mfma_f4 c) {
+  if constexpr (std::is_same<ST, F16>::value)
+    return __builtin_amdgcn_mfma_f32_4x4x4f16(__builtin_bit_cast(mfma_h4, a),
+                                              __builtin_bit_cast(mfma_h4, b), c, 0, 0, 0);
+  else
+    return __builtin_amdgcn_mfma_f32_4x4x4bf16_1k(__builtin_bit_cast(mfma_s4, a),
+                                                  __builtin_bit_cast(mfma_s4, b), c, 0, 0, 0);
+}
+
+// acc must be zero on entry (the gather stores and clears it every tile); it receives the sums.
+template <typename ST, int QT, int R>
+__device__ __forceinline__ void accumulate_dense_mfma(const IndexView& ix, const DenseEntry* de,
+                                                      int n, int64_t first,
+                                                      float (&acc)[QT][R]) {
+  static_assert(QT % 4 == 0 && R % 2 == 0, "4-query groups, pairs of documents");
+  constexpr int NW = R / 2;  // words of two 16-bit scores per entry and lane
+  constexpr int QG = QT / 4;
+  const uint16_t* dense = reinterpret_cast<const uint16_t*>(ix.dense) + first;
+  const int qs = lane() & 3;
+  uint32_t w[2][4][NW];
+  uint32_t mk[2][4];
+  float mu[2][4];
+  auto load_group = [&](int e0, uint32_t (&dst)[4][NW], uint32_t (&m)[4], float (&f)[4]) {
+#pragma unroll
+    for (int u = 0; u < 4; ++u) {
+      const int e = (e0 + u < n) ? e0 + u : n - 1;  // clamped: always a valid row
+      const DenseEntry d = de[e];
+      const uint32_t* q = reinterpret_cast<const uint32_t*>(dense + (int64_t)d.row * ix.n_pad);
+      if constexpr (NW % 4 == 0) {
+#pragma unroll
+        for (int i = 0; i < NW / 4; ++i) {
+          const uint4 x = reinterpret_cast<const uint4*>(q)[i];
+          dst[u][4 * i] = x.x;
+          dst[u][4 * i + 1] = x.y;
+          dst[u][4 * i + 2] = x.z;
+          dst[u][4 * i + 3] = x.w;
+        }
+      } else if constexpr (NW == 2) {
+        const uint2 x = reinterpret_cast<const uint2*>(q)[0];
+        dst[u][0] = x.x;
+        dst[u][1] = x.y;
+      } else {
+        dst[u][0] = q[0];
+      }
+      m[u] = (e0 + u < n) ? d.qmask : 0u;  // entries past the end add nothing
+      f[u] = d.mult;
+    }
+  };
+  if (n <= 0) return;
+  // the sums as the instruction's columns: ca[g][j] = queries 4g..4g+3 at document j (acc is
+  // zero on entry, so they start at zero and replace acc at the end)
+  mfma_f4 ca[QG][R];
+#pragma unroll
+  for (int g = 0; g < QG; ++g)
+#pragma unroll
+    for (int j = 0; j < R; ++j) ca[g][j] = mfma_f4{0.f, 0.f, 0.f, 0.f};
+  load_group(0, w[0], mk[0], mu[0]);
+  for (int e0 = 0; e0 < n; e0 += 8) {
+#pragma unroll
+    for (int h = 0; h < 2; ++h) {
+      const int eg = e0 + 4 * h;
+      if (eg >= n) break;
+      if (eg + 4 < n) load_group(eg + 4, w[h ^ 1], mk[h ^ 1], mu[h ^ 1]);
+      uint32_t mb[4];
+#pragma unroll
+      for (int u = 0; u < 4; ++u) mb[u] = mult_bits16<ST>(mu[h][u]);
+#pragma unroll
+      for (int g = 0; g < QG; ++g) {
+        const int q = 4 * g + qs;
+        uint32_t av[4];
+#pragma unroll
+        for (int u = 0; u < 4; ++u) av[u] = ((mk[h][u] >> q) & 1u) ? mb[u] : 0u;
+        const mfma_u2 a = {av[0] | (av[1] << 16), av[2] | (av[3] << 16)};
+#pragma unroll
+        for (int j = 0; j < R; ++j) {
+          uint32_t bv[4];
+#pragma unroll
+          for (int u = 0; u < 4; ++u)
+            bv[u] = (j & 1) ? (w[h][u][j >> 1] >> 16) : (w[h][u][j >> 1] & 0xFFFFu);
+          const mfma_u2 b = {bv[0] | (bv[1] << 16), bv[2] | (bv[3] << 16)};
+          ca[g][j] = mfma_4x4x4<ST>(a, b, ca[g][j]);
+        }
+      }
+    }
+  }
+#pragma unroll
+  for (int g = 0; g < QG; ++g)
+#pragma unroll
+    for (int j = 0; j < R; ++j)
+#pragma unroll
+      for (int v = 0; v < 4; ++v) acc[4 * g + v][j] = ca[g][j][v];
+}
+
 template <typename ST, int QT, int R>
 __device__ __forceinline__ void accumulate_dense(const IndexView& ix, const DenseEntry* de, int n,
                                                  int64_t first, float (&acc)[QT][R]) {
+  if constexpr (kDenseMfma && sizeof(typename ST::T) == 2 && QT % 4 == 0 && R % 2 == 0) {
+    // only the gather's tiles (QT >= 4) come here, with acc cleared by the previous tile's store
+    accumulate_dense_mfma<ST, QT, R>(ix, de, n, first, acc);
+    return;
+  }
   if constexpr (std::is_same<ST, F16>::value) {
     accumulate_dense_f16<QT, R>(ix, de, n, first, acc);
     return;

@@ -15,6 +15,16 @@ def _dev(a):
     return torch.from_numpy(np.ascontiguousarray(a)).cuda()
 
 
+def _settled_allocated():
+    """PyTorch's allocated bytes once earlier tests' garbage (tensors held by reference cycles,
+    e.g. through exception tracebacks) is collected, so that only this test moves the count."""
+    import gc
+    import torch
+    gc.collect()
+    torch.cuda.synchronize()
+    return torch.cuda.memory_allocated()
+
+
 def test_torch_allocator_holds_the_index_memory():
     """With the default allocator every device byte of the index (arrays, then the search arena
     the first batch grows) comes from PyTorch's caching allocator, and free gives it back."""
@@ -26,8 +36,7 @@ def test_torch_allocator_holds_the_index_memory():
     out = (torch.empty((q.n, 10), dtype=torch.int32, device="cuda"),
            torch.empty((q.n, 10), dtype=torch.float32, device="cuda"),
            torch.empty(q.n, dtype=torch.int32, device="cuda"))
-    torch.cuda.synchronize()
-    before = torch.cuda.memory_allocated()
+    before = _settled_allocated()
     idx = Index(tok, off, c.vocab, 1.5, 0.75, 0.0, "lucene", "f16")
     torch.cuda.synchronize()
 
@@ -58,8 +67,7 @@ def test_hip_malloc_without_allocator():
     c = make_corpus(0, n_docs=5_000)
     q = make_queries(0, n_queries=32, vocab=c.vocab)
     tok, off, qd = _dev(c.tokens), _dev(c.doc_offsets), _dev(q.q_ids)
-    torch.cuda.synchronize()
-    before = torch.cuda.memory_allocated()
+    before = _settled_allocated()
     a = Index(tok, off, c.vocab, 1.5, 0.75, 0.0, "lucene", "f32", allocator=None)
     assert torch.cuda.memory_allocated() == before
     b = Index(tok, off, c.vocab, 1.5, 0.75, 0.0, "lucene", "f32")

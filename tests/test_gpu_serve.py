@@ -116,6 +116,8 @@ def test_budget_reserved_at_create_and_held(setup):
     import torch
     from paper_2407_03618_amd import Server
     c, q, idx, ref = setup
+    import gc
+    gc.collect()  # earlier tests' cyclic garbage must not be freed inside the measured span
     torch.cuda.synchronize()
     before = torch.cuda.memory_allocated()
     idx_before = idx.device_bytes()

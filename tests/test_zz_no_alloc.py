@@ -61,6 +61,8 @@ def test_noalloc_matches_batched_search_twice_then_smaller():
                torch.empty(n, dtype=torch.int32, device="cuda")]
         assert _call(lib.bm25_search_batch, idx, qd, off, kk, k_max, ref) == 0
     del ref
+    import gc
+    gc.collect()  # earlier tests' cyclic garbage must not be freed inside the measured span
     torch.cuda.synchronize()
     held = torch.cuda.memory_allocated()
     idx_bytes = idx.device_bytes()
