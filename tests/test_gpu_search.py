@@ -46,6 +46,32 @@ def test_config0_all_queries(cfg0, form, dtype):
     check_batch(ref, q.q_ids, q.q_offsets, q.k, ids, sc, cnt, RTOL[dtype], f"{form}/{dtype}")
 
 
+@pytest.mark.parametrize("dtype,reps", [("bf16", 300), ("bf16", 2047), ("f16", 2047),
+                                        ("f32", 300)])
+def test_repeated_dense_token(cfg0, dtype, reps):
+    """A query repeating a dense-row token more often than the bf16 matrix-core operand holds
+    exactly (2^8): the planner splits its multiplicity over several entries of the same row. In
+    fp16 every multiplicity a query can have (at most 2048 ids) is exact, which the longest query
+    checks. Neighbours in the batch share the row with other multiplicities."""
+    c, _ = cfg0
+    ref = eager.build_index(c.tokens, c.doc_offsets, c.vocab, 1.5, 0.75, 0.0, "lucene")
+    df = np.diff(ref.indptr)
+    dense_tok = int(np.argmax(df))  # the most frequent token: a dense row at any threshold
+    assert df[dense_tok] * 16 >= c.n_docs
+    other = int(np.argsort(df)[-2])
+    queries = [np.array([dense_tok] * reps + [other], np.int32),
+               np.array([dense_tok, other], np.int32),
+               np.array([dense_tok] * 3, np.int32),
+               np.array([other] * reps, np.int32)]
+    off = np.zeros(len(queries) + 1, np.int64)
+    off[1:] = np.cumsum([q.size for q in queries])
+    qb = QueryBatch(np.concatenate(queries), off, np.full(len(queries), 10, np.int32))
+    idx = _index(c, dtype=dtype)
+    ids, sc, cnt = _run(idx, qb, 10, "batch")
+    check_batch(ref, qb.q_ids, qb.q_offsets, qb.k, ids, sc, cnt, RTOL[dtype], f"x{reps} {dtype}")
+    idx.free()
+
+
 VARIANTS = [("bm25plus", 1.2, 0.75, 1.0), ("bm25l", 1.2, 0.75, 0.5), ("robertson", 1.2, 0.75, 0.0),
             ("atire", 1.2, 0.75, 0.0), ("tfldp", 1.2, 0.75, 0.5), ("lucene", 0.9, 0.4, 0.0)]
 
