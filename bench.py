@@ -37,7 +37,8 @@ HBM_PEAK_GBS = 8000.0
 VALU_PEAK_TOPS = 256 * 64 * 2.4e9 / 1e12
 KERNEL_SOURCES = ["paper_2407_03618_amd/csrc/search_kernels.hpp",
                   "paper_2407_03618_amd/csrc/device.hpp",
-                  "paper_2407_03618_amd/csrc/search_inst.hip"]
+                  "paper_2407_03618_amd/csrc/search_inst.hip",
+                  "paper_2407_03618_amd/build.py"]  # its compiler flags shape the kernel too
 TRAFFIC_FILE = os.path.join(ROOT, "profiles", "k_gather_8.8M-docs_4096-query_top100_f16_traffic.json")
 DENSE_FRACTION = 16        # rows of tokens in >= N/16 documents also have a dense copy
 DENSE_PAD = 4096           # dense rows are padded to a multiple of this many documents

@@ -466,9 +466,10 @@ __global__ __launch_bounds__(256) void k_keys_hist(const int32_t* __restrict__ t
       if (valid)
         keys[p] = ((uint64_t)(uint32_t)t << L.tok_shift) | ((uint64_t)doc << L.doc_shift) |
                   (L.len_bits > 0 ? (uint64_t)len : 0ull);
-      const uint32_t d = (uint32_t)t & mask0;
-      const uint64_t peers = match_digit8(d) & ballot(valid);
-      if (valid && __builtin_ctzll(peers) == l) atomicAdd(&h[d], (uint32_t)__popcll(peers));
+      // the first digit is the token's low bits, spread enough that one LDS atomic per key costs
+      // less than matching equal digits across the wave (the higher digits, mostly zero under a
+      // Zipf law, are counted with the match in k_radix_hist)
+      if (valid) atomicAdd(&h[(uint32_t)t & mask0], 1u);
       dcur = (int64_t)readlane((uint32_t)doc, 63);
     }
   }
