@@ -288,8 +288,11 @@ __global__ __launch_bounds__(256) void k_radix_hist(const uint64_t* __restrict__
   for (int r = 0; r < kRadixRounds; ++r) {
     const bool valid = base + r * 64 + l < n;
     const uint32_t d = (uint32_t)(key[r] >> shift) & mask;
-    const uint64_t peers = match_digit8(d) & ballot(valid);
-    if (valid && __builtin_ctzll(peers) == l) atomicAdd(&h[d], (uint32_t)__popcll(peers));
+    // the digits above the first are mostly zero (small token ids dominate under a Zipf law):
+    // zeros are counted with one ballot, the other digits, spread out, with an LDS atomic each
+    const uint64_t zeros = ballot(valid && d == 0u);
+    if (valid && d != 0u) atomicAdd(&h[d], 1u);
+    if (l == 0 && zeros) atomicAdd(&h[0], (uint32_t)__popcll(zeros));
   }
   __syncthreads();
   hist[(int64_t)threadIdx.x * nblk + blockIdx.x] = h[threadIdx.x];
@@ -467,8 +470,7 @@ __global__ __launch_bounds__(256) void k_keys_hist(const int32_t* __restrict__ t
         keys[p] = ((uint64_t)(uint32_t)t << L.tok_shift) | ((uint64_t)doc << L.doc_shift) |
                   (L.len_bits > 0 ? (uint64_t)len : 0ull);
       // the first digit is the token's low bits, spread enough that one LDS atomic per key costs
-      // less than matching equal digits across the wave (the higher digits, mostly zero under a
-      // Zipf law, are counted with the match in k_radix_hist)
+      // less than matching equal digits across the wave
       if (valid) atomicAdd(&h[(uint32_t)t & mask0], 1u);
       dcur = (int64_t)readlane((uint32_t)doc, 63);
     }
