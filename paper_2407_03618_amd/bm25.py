@@ -251,10 +251,10 @@ class Index:
             load_library().bm25_index_free(self._h)
             self._h = None
 
-    def __del__(self):
+    def __del__(self, _finalizing=sys.is_finalizing):
         # at interpreter exit the allocator callbacks can no longer run: leave the memory to
-        # the process teardown
-        if sys.is_finalizing():
+        # the process teardown (the check is bound here: module globals may be gone by then)
+        if _finalizing():
             return
         try:
             self.free()
@@ -464,8 +464,8 @@ class Server:
             _check(load_library().bm25_serve_destroy(self._h))
             self._h = None
 
-    def __del__(self):
-        if sys.is_finalizing():
+    def __del__(self, _finalizing=sys.is_finalizing):
+        if _finalizing():
             return
         try:
             self.close()
@@ -543,8 +543,8 @@ class Vocab:
             load_library().bm25_vocab_free(self._h)
             self._h = None
 
-    def __del__(self):
-        if sys.is_finalizing():
+    def __del__(self, _finalizing=sys.is_finalizing):
+        if _finalizing():
             return
         try:
             self.free()
