@@ -2,15 +2,19 @@
 //
 // Steps (Section 2 "Calculation of BM25", "Eager index-time scoring", "Efficient Matrix
 // Sparsity"; Section 2.1 for shifted variants):
-//   1. validate offsets and token ids on the device, |D| per document, sum |D| in int64;
-//   2. one 64-bit key per token position: (token << 32) | document;
+//   1. validate the offsets on the device: |D| per document, sum |D| in int64, the longest
+//      document, the document at every 1024th position;
+//   2. one 64-bit key per token position, token | document | |D| (KeyLayout), with the first radix
+//      histogram and the token id range check in the same pass;
 //   3. stable LSD radix sort of the keys by the token bits (digits of at most 8 bits, each pass
 //      ranked in LDS and written out as contiguous runs); positions arrive in document order, so
 //      equal tokens stay ordered by document;
-//   4. run-length encoding of equal keys: one stored pair per distinct (t, D), TF = run length;
-//   5. indptr from the first pair of every token, DF = segment length, IDF in FP64;
-//   6. per-pair score S(t, D) (or S - S_theta) in FP32, rounded to the storage type;
-//   7. skip table of long rows (first entry at or after each document block).
+//   4. run-length encoding of equal keys: one stored pair per distinct (t, D), TF = run length,
+//      and indptr from the first pair of every token;
+//   5. DF = row length, IDF in FP64, long rows, dense-row candidates (chosen on the host: few);
+//   6. per-pair score S(t, D) (or S - S_theta) in FP32, rounded to the storage type, with the
+//      skip table of long rows (first entry at or after each document block) and the dense rows
+//      written from the same pass.
 #include <hip/hip_runtime.h>
 
 #include <algorithm>
