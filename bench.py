@@ -214,6 +214,46 @@ def plain_1m_leg(nq: int, n_check: int) -> dict:
     return res, dict(queries=[q.query(i).copy() for i in sample], rows=rows, k=100)
 
 
+def tokenize_leg(n_docs: int, n_check: int, n_queries: int = 4096) -> tuple:
+    """Tokenization in front of the path (Section 2, "Tokenization"): a seeded multi-script UTF-8
+    corpus split on the GPU into words of two or more word characters, lowercased, with a device
+    dictionary giving first-occurrence ids (timed after one untimed run); then query texts mapped
+    through the dictionary. Keeps the GPU's words of sampled documents, to be checked against the
+    oracle's split (the words behind the ids, which do not depend on the order ids are given)."""
+    import torch
+    from paper_2407_03618_amd import Vocab
+    from workloads.text import make_text_corpus, make_text_queries
+    lexicon = 200_000
+    c = make_text_corpus(n_docs, seed=11, lexicon=lexicon)
+    q = make_text_queries(n_queries, seed=12, lexicon=lexicon, corpus_seed=11)
+    dev = torch.device("cuda:0")
+    text, off = torch.from_numpy(c.data).to(dev), torch.from_numpy(c.offsets).to(dev)
+    qt, qo = torch.from_numpy(q.data).to(dev), torch.from_numpy(q.offsets).to(dev)
+    Vocab(text, off, lowercase=True).free()  # first run: grows the caching allocator
+    torch.cuda.synchronize()
+    t0 = time.perf_counter()
+    v = Vocab(text, off, lowercase=True)
+    torch.cuda.synchronize()
+    el = time.perf_counter() - t0
+    v.map(qt, qo)
+    torch.cuda.synchronize()
+    t0 = time.perf_counter()
+    qids, _ = v.map(qt, qo)
+    torch.cuda.synchronize()
+    mel = time.perf_counter() - t0
+    ids, doff = v.corpus()
+    ids, doff = ids.cpu().numpy(), doff.cpu().numpy()
+    words = v.words()
+    sample = _spread(0, n_docs, n_check)
+    rows = [(c.doc(d), [words[i] for i in ids[doff[d]:doff[d + 1]]]) for d in sample]
+    res = dict(docs=n_docs, bytes=int(c.data.size), tokens=v.n_tokens, vocab=v.vocab_size,
+               ms=el * 1e3, GB_per_s=c.data.size / el / 1e9, tokens_per_s=v.n_tokens / el,
+               map_queries=n_queries, map_ids=int(qids.numel()), map_ms=mel * 1e3,
+               map_queries_per_s=n_queries / mel, lowercase=True)
+    v.free()
+    return res, dict(rows=rows)
+
+
 def long_docs_leg(n_check: int, n_batches: int = 4, batch: int = 512) -> tuple:
     """The shifted-variant workload at full size: 5M long documents (mean 300 ids, V = 3M,
     Zipf 1.0), BM25+ (delta = 1) and BM25L (delta = 0.5), k1 = 1.2, b = 0.75, bf16 scores,
@@ -534,6 +574,19 @@ def cpu_baseline_leg(corpus, queries, time_idx, single_idx, checks, bg, threads)
         parity[f"cfg3_{v}"] = _parity_stats(errs, len(res["files"]), RTOL["bf16"], fails)
         parity[f"cfg3_{v}"]["oracle_build_s"] = res["build_s"]
         log(f"[parity cfg3_{v}]", parity[f"cfg3_{v}"])
+    # tokenization: the GPU's words of sampled documents against the oracle's split
+    c = checks.get("tokenize")
+    if c is not None:
+        from oracle import tokenize as T
+        fails, n_tok = [], 0
+        for j, (doc, got) in enumerate(c["rows"]):
+            want = T.split(doc, lowercase=True)
+            n_tok += len(want)
+            if got != want:
+                fails.append(f"document sample {j}: {len(got)} words, oracle {len(want)}")
+        parity["tokenize"] = dict(docs_checked=len(c["rows"]), tokens_checked=n_tok,
+                                  ok=not fails, failures=fails[:3])
+        log("[parity tokenize]", parity["tokenize"])
     if bg is not None:
         import shutil
         shutil.rmtree(bg[2], ignore_errors=True)
@@ -558,6 +611,9 @@ def main():
     ap.add_argument("--serve-warmup", type=float, default=1.0)
     ap.add_argument("--no-cpu", action="store_true")
     ap.add_argument("--no-plain", action="store_true")
+    ap.add_argument("--no-tokenize", action="store_true")
+    ap.add_argument("--tokenize-docs", type=int, default=500_000,
+                    help="documents of the seeded text corpus the tokenization leg splits")
     ap.add_argument("--no-serve", action="store_true")
     ap.add_argument("--no-long", action="store_true", help="skip the 5M long-document leg")
     ap.add_argument("--no-graph", action="store_true", help="skip the HIP graph leg")
@@ -767,6 +823,11 @@ def main():
         log("[plain 1M f32]", extra["plain_1M_fp32"])
     idx32.free()  # make room for the 5M-document indexes
     torch.cuda.empty_cache()
+
+    if not args.no_tokenize:
+        extra["tokenize"], checks["tokenize"] = tokenize_leg(args.tokenize_docs, args.check)
+        log("[tokenize]", extra["tokenize"])
+        torch.cuda.empty_cache()
 
     if not args.no_long:
         legs, lchecks, lq = long_docs_leg(args.check_long)
