@@ -13,8 +13,9 @@
 //      simple lowercase mapping, and U+0130 becomes "i" followed by U+0307 (not a word
 //      character), so a run ends after it;
 //   3. a run starts at a word character whose predecessor does not continue a run; one thread
-//      walks each run, counts its code points and hashes them (64-bit FNV-1a, finalised with the
-//      splitmix64 mixer); runs of two or more code points are the tokens;
+//      walks each run, counts its code points and hashes them (64-bit FNV-1a with one round per
+//      code point, finalised with the splitmix64 mixer); runs of two or more code points are the
+//      tokens;
 //   4. tokens go into an open-addressing hash table keyed by their hash; the table records each
 //      word's first token; every token is then compared with its word's first token code point
 //      by code point, so two words with the same 64-bit hash are detected (an error, not a merge);
@@ -111,6 +112,14 @@ __device__ __forceinline__ Char char_at(const uint8_t* t, int64_t i, int64_t hi,
   c.word = false;
   c.joins = false;
   if (c.len == 0) return c;
+  if (c.cp < 0x80u) {
+    // ASCII, most of most text: the tables' answers, without their lookups (letters map A-Z to
+    // a-z; word characters are letters, digits and the underscore)
+    if (lower && c.cp - 'A' < 26u) c.cp += 32u;
+    c.word = (c.cp - 'a' < 26u) || (c.cp - 'A' < 26u) || (c.cp - '0' < 10u) || c.cp == '_';
+    c.joins = c.word;
+    return c;
+  }
   bool split_after = false;
   if (lower) {
     if (c.cp == 0x130u) {
@@ -137,11 +146,10 @@ __device__ __forceinline__ bool prev_joins(const uint8_t* t, int64_t lo, int64_t
 }
 
 __device__ __forceinline__ uint64_t hash_step(uint64_t h, uint32_t cp) {
-#pragma unroll
-  for (int k = 0; k < 4; ++k) {
-    h ^= (cp >> (8 * k)) & 0xFFu;
-    h *= 0x100000001b3ull;
-  }
+  // one FNV-1a round per code point (the whole code point, not its bytes: one 64-bit multiply
+  // per character); hash_final's mixer spreads the bits
+  h ^= cp;
+  h *= 0x100000001b3ull;
   return h;
 }
 
@@ -273,10 +281,15 @@ __global__ __launch_bounds__(kThreads) void k_insert(const Run* toks, int64_t n_
   const unsigned long long h = toks[t].hash;
   int64_t s = (int64_t)(h & (uint64_t)(cap - 1));
   for (int64_t probe = 0; probe < cap; ++probe) {
-    const unsigned long long k = atomicCAS(keys + s, (unsigned long long)kEmpty, h);
+    // a plain read first: a frequent word's slot is found filled by almost all of its tokens,
+    // which then skip the atomic (same-address atomics from millions of tokens serialize)
+    unsigned long long k = __hip_atomic_load(keys + s, __ATOMIC_RELAXED, __HIP_MEMORY_SCOPE_AGENT);
+    if (k == kEmpty) k = atomicCAS(keys + s, (unsigned long long)kEmpty, h);
     if (k == kEmpty || k == h) {
       if (k == kEmpty) atomicAdd(status, 1u);
-      atomicMin(first + s, (uint32_t)t);
+      // first only decreases: a token at or after the value read needs no update
+      if ((uint32_t)t < __hip_atomic_load(first + s, __ATOMIC_RELAXED, __HIP_MEMORY_SCOPE_AGENT))
+        atomicMin(first + s, (uint32_t)t);
       tok_slot[t] = (uint32_t)s;
       return;
     }
