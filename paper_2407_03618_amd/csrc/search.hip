@@ -174,21 +174,30 @@ static int64_t gather_lds(const TileShape& t, int64_t ecap, int64_t pcap) {
 TileShape choose_shape(const bm25_index* idx, int32_t n, int32_t max_qlen, int32_t k_max) {
   TileShape t;
   const int kpl = kpl_for(k_max);
-  // measured best on 8.8M documents, 4096 queries, top-100: 4 waves, 4 documents per lane,
-  // 8 queries per tile
+  // measured best on the 8.8M-document index, for the benchmark's batches (up to 30 ids per
+  // query, top-100) and the serving recipe's (up to 64 ids, top-10/100/1000) alike, at 1024 to
+  // 4096 queries per batch: 4 waves, 4 documents per lane, 4 queries per tile (8-query tiles
+  // were 20-40% slower)
   t.waves = 4;
   t.doc_tile = 1024;
-  t.q_tile = fit_q_tile(8, kpl, 4, 4);
+  t.q_tile = fit_q_tile(4, kpl, 4, 4);
   // long queries: fewer queries per tile so that accumulators and entry state fit in LDS
   auto fits = [&](const TileShape& s) {
     const int64_t pc = std::min<int64_t>((int64_t)s.q_tile * max_qlen, kTileMaxPositions);
     return gather_lds(s, pc + s.waves, pc) <= 96 * 1024;
   };
   while (!fits(t) && t.q_tile > t.waves) t.q_tile = fit_q_tile(t.q_tile / 2, kpl, 4, 4);
+  // document groups: about 4096 workgroups in all for lists of up to 256 keys, half that for
+  // each doubling beyond (each group keeps and merges its own lists, which costs more the
+  // longer they are); at least 8 and a multiple of 8 (one share per XCD), at most 2048 / (keys
+  // per list / 64). Measured best on the same index: top-10 and top-100 batches of 128, 256,
+  // 1024 and 2048 queries at 4096 workgroups; top-1000 batches of 64, 256 and 1024 queries at
+  // 64, 16 and 8 groups.
   const int64_t ntiles = std::max<int64_t>(1, (n + t.q_tile - 1) / t.q_tile);
-  int64_t g = (1024 + ntiles - 1) / ntiles;
+  const int64_t target = 4096 / std::max(1, kpl / 4);
+  int64_t g = (target + ntiles - 1) / ntiles;
   g = ((g + 7) / 8) * 8;
-  g = std::min<int64_t>(std::max<int64_t>(g, 8), 512);
+  g = std::min<int64_t>(std::max<int64_t>(g, 8), std::min<int64_t>(512, 2048 / kpl));
   const int64_t tiles = std::max<int64_t>(1, (idx->n_docs + t.doc_tile - 1) / t.doc_tile);
   g = std::min<int64_t>(g, tiles);
   t.doc_groups = (int)g;
