@@ -187,17 +187,33 @@ TileShape choose_shape(const bm25_index* idx, int32_t n, int32_t max_qlen, int32
     return gather_lds(s, pc + s.waves, pc) <= 96 * 1024;
   };
   while (!fits(t) && t.q_tile > t.waves) t.q_tile = fit_q_tile(t.q_tile / 2, kpl, 4, 4);
-  // document groups: about 4096 workgroups in all for lists of up to 256 keys, half that for
-  // each doubling beyond (each group keeps and merges its own lists, which costs more the
-  // longer they are); at least 8 and a multiple of 8 (one share per XCD), at most 2048 / (keys
-  // per list / 64). Measured best on the same index: top-10 and top-100 batches of 128, 256,
-  // 1024 and 2048 queries at 4096 workgroups; top-1000 batches of 64, 256 and 1024 queries at
-  // 64, 16 and 8 groups.
+  // document groups. Each group keeps and merges its own lists, which costs more the longer
+  // they are, so long lists take fewer groups: about 4096 workgroups in all and at least 8
+  // groups for lists of up to 256 keys, 2048 and at least 4 for 512 keys, and for 1024 keys
+  // 2048 (batches of 256 tiles and more) or 1024 and at least 2. Counts of 8 and above are
+  // multiples of 8 (one share per XCD), smaller ones powers of two; at most 2048 / (keys per
+  // list / 64). Measured best on the same index: top-10 and top-100 batches of 128 to 4096
+  // queries at 4096 workgroups and 8 groups or more; top-500 batches of 1024, 2048 and 4096
+  // queries at 8, 4-8 and 4 groups; top-1000 batches of 64, 256, 1024, 2048 and 4096 queries
+  // at 64, 16, 8, 4 and 2 groups (4096 queries: 65.7 ms against 80.7 with 8 groups).
   const int64_t ntiles = std::max<int64_t>(1, (n + t.q_tile - 1) / t.q_tile);
-  const int64_t target = 4096 / std::max(1, kpl / 4);
-  int64_t g = (target + ntiles - 1) / ntiles;
-  g = ((g + 7) / 8) * 8;
-  g = std::min<int64_t>(std::max<int64_t>(g, 8), std::min<int64_t>(512, 2048 / kpl));
+  int64_t target = 4096, gmin = 8;
+  if (kpl == 8) {
+    target = 2048;
+    gmin = 4;
+  } else if (kpl > 8) {
+    target = ntiles >= 256 ? 2048 : 1024;
+    gmin = 2;
+  }
+  int64_t g = std::max<int64_t>((target + ntiles - 1) / ntiles, gmin);
+  if (g >= 8) {
+    g = ((g + 7) / 8) * 8;
+  } else {
+    int64_t p2 = 1;
+    while (p2 < g) p2 *= 2;
+    g = p2;
+  }
+  g = std::min<int64_t>(g, std::min<int64_t>(512, 2048 / kpl));
   const int64_t tiles = std::max<int64_t>(1, (idx->n_docs + t.doc_tile - 1) / t.doc_tile);
   g = std::min<int64_t>(g, tiles);
   t.doc_groups = (int)g;
