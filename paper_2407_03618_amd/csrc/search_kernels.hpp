@@ -1265,12 +1265,23 @@ __device__ __forceinline__ void map_block(int bid, int n_groups, int& tile, int&
   }
 }
 
-// With 4 waves, 1024-key lists need about 143 VGPRs (3 waves per SIMD); held to 128 (4 waves)
-// the compiler spills 10 to 27 registers, and the fp16 kernel is still 10-13% faster (top-1000
-// on 8.8M documents, 1024 to 4096 queries per batch)
+// With 4 waves, 1024-key lists need about 143 VGPRs (3 waves per SIMD). The fp16 form is held
+// to 128 (4 waves): the compiler spills about 10 registers, and the kernel is still 10-13%
+// faster (top-1000 on 8.8M documents, 1024 to 4096 queries of up to 64 ids per batch). The bf16
+// form spills more and was 8% slower so (top-1000 on 5M long documents, 30-200-id queries).
+template <typename ST>
+struct LongListFourWaves {
+  static constexpr bool value = false;
+};
+template <>
+struct LongListFourWaves<F16> {
+  static constexpr bool value = true;
+};
+
 template <int W, int QT, int R, int KPL, typename ST>
 __global__ __launch_bounds__(W * 64)
-__attribute__((amdgpu_waves_per_eu((KPL >= 16 && W == 4) ? 4 : 1))) void k_gather(GatherArgs a) {
+__attribute__((amdgpu_waves_per_eu((KPL >= 16 && W == 4 && LongListFourWaves<ST>::value) ? 4 : 1)))
+void k_gather(GatherArgs a) {
   constexpr int DT = W * 64 * R;
   constexpr int KP = KPL * 64;
   constexpr int QPW = QT / W;
