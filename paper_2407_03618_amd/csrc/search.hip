@@ -190,20 +190,20 @@ TileShape choose_shape(const bm25_index* idx, int32_t n, int32_t max_qlen, int32
   // document groups. Each group keeps and merges its own lists, which costs more the longer
   // they are, so long lists take fewer groups: about 4096 workgroups in all and at least 8
   // groups for lists of up to 256 keys, 2048 and at least 4 for 512 keys, and for 1024 keys
-  // 2048 (batches of 256 tiles and more) or 1024 and at least 4. Counts of 8 and above are
+  // 2048 (batches of 128 tiles and more) or 1024 and at least 4. Counts of 8 and above are
   // multiples of 8 (one share per XCD), smaller ones powers of two; at most 2048 / (keys per
   // list / 64). Measured best on the same index: top-10 and top-100 batches of 128 to 4096
   // queries at 4096 workgroups and 8 groups or more; top-500 batches of 1024, 2048 and 4096
-  // queries at 8, 4-8 and 4 groups; top-1000 batches of 64, 256, 1024, 2048 and 4096 queries
-  // at 64, 16, 8, 4 and 4 groups (4096 queries: 59.8 ms, against 66.3 with 2 groups and 80.7
-  // with 8 before the gather's long-list form ran at 4 waves per SIMD).
+  // queries at 8, 4-8 and 4 groups; top-1000 batches of 64, 256, 512, 1024, 2048 and 4096
+  // queries at 64, 16, 16, 8, 4 and 4 groups (4096 queries: 59.7 ms, against 66.3 with 2 groups
+  // and 68.5 with 8).
   const int64_t ntiles = std::max<int64_t>(1, (n + t.q_tile - 1) / t.q_tile);
   int64_t target = 4096, gmin = 8;
   if (kpl == 8) {
     target = 2048;
     gmin = 4;
   } else if (kpl > 8) {
-    target = ntiles >= 256 ? 2048 : 1024;
+    target = ntiles >= 128 ? 2048 : 1024;
     gmin = 4;
   }
   int64_t g = std::max<int64_t>((target + ntiles - 1) / ntiles, gmin);
