@@ -188,17 +188,18 @@ TileShape choose_shape(const bm25_index* idx, int32_t n, int32_t max_qlen, int32
   };
   while (!fits(t) && t.q_tile > t.waves) t.q_tile = fit_q_tile(t.q_tile / 2, kpl, 4, 4);
   // document groups. Each group keeps and merges its own lists, which costs more the longer
-  // they are, so long lists take fewer groups: about 4096 workgroups in all and at least 8
-  // groups for lists of up to 256 keys, 2048 and at least 4 for 512 keys, and for 1024 keys
-  // 2048 (batches of 128 tiles and more) or 1024 and at least 4. Counts of 8 and above are
-  // multiples of 8 (one share per XCD), smaller ones powers of two; at most 2048 / (keys per
-  // list / 64). Measured best on the same index: top-10 and top-100 batches of 128 to 4096
-  // queries at 4096 workgroups and 8 groups or more; top-500 batches of 1024, 2048 and 4096
-  // queries at 8, 4-8 and 4 groups; top-1000 batches of 64, 256, 512, 1024, 2048 and 4096
-  // queries at 64, 16, 16, 8, 4 and 4 groups (4096 queries: 59.7 ms, against 66.3 with 2 groups
-  // and 68.5 with 8).
+  // they are, so long lists take fewer groups. Lists of up to 256 keys: about 4096 workgroups
+  // in all (2048 for batches of fewer than 64 tiles) and at least 8 groups; 512 keys: 2048 and
+  // at least 4; 1024 keys: 2048 (batches of 128 tiles and more) or 1024, and at least 4. Counts
+  // of 8 and above are multiples of 8 (one share per XCD), smaller ones powers of two; at most
+  // 2048 / (keys per list / 64). Measured best on the same index: top-10 and top-100 batches of
+  // 256 to 4096 queries at 4096 workgroups and 8 groups or more, of 16 to 128 queries at 2048
+  // (64 queries, top-100: 1.22 ms against 1.36 with 4096); top-500 batches of 1024, 2048 and
+  // 4096 queries at 8, 4-8 and 4 groups; top-1000 batches of 64, 256, 512, 1024, 2048 and 4096
+  // queries at 64, 16, 16, 8, 4 and 4 groups (4096 queries: 59.7 ms, against 66.3 with 2
+  // groups and 68.5 with 8).
   const int64_t ntiles = std::max<int64_t>(1, (n + t.q_tile - 1) / t.q_tile);
-  int64_t target = 4096, gmin = 8;
+  int64_t target = ntiles < 64 ? 2048 : 4096, gmin = 8;
   if (kpl == 8) {
     target = 2048;
     gmin = 4;
