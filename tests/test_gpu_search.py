@@ -152,6 +152,24 @@ def test_scaled_corpus_many_tiles_and_groups(form, k):
                 sample=sample)
 
 
+@pytest.mark.parametrize("groups", [2, 4, 8])
+def test_long_lists_over_few_groups(groups):
+    """1024-key lists at fp16 (the gather form held to 4 waves per SIMD) over few document groups,
+    as the automatic shape gives large top-1000 batches; fewer than 8 groups take the plain
+    block-to-group mapping. Per-query k mixes 1000 with shorter lists in the same batch."""
+    c = make_corpus(2, n_docs=120_000)
+    q0 = make_queries(2, n_queries=77, vocab=c.vocab, k=1000)
+    kk = np.array([1000, 10, 100, 999, 1000, 257, 64], dtype=np.int32)[np.arange(q0.n) % 7]
+    q = QueryBatch(q0.q_ids, q0.q_offsets, kk)
+    ref = eager.build_index(c.tokens, c.doc_offsets, c.vocab, token_subset=np.unique(q.q_ids))
+    idx = _index(c, dtype="f16")
+    idx.set_plan(dict(q_tile=4, waves=4, doc_tile=1024, doc_groups=groups))
+    ids, sc, cnt = _run(idx, q, 1000, "batch")
+    idx.set_plan(None)
+    check_batch(ref, q.q_ids, q.q_offsets, q.k, ids, sc, cnt, RTOL["f16"], f"groups={groups}",
+                sample=range(0, q.n, 4))
+
+
 def test_batched_shapes_agree():
     """Every built launch shape, with and without the dense head rows, gives results within
     tolerance; invalid shapes are rejected."""
