@@ -12,8 +12,9 @@
 //      or "_", over the whole code space); with lowercasing each code point first takes its
 //      simple lowercase mapping, and U+0130 becomes "i" followed by U+0307 (not a word
 //      character), so a run ends after it;
-//   3. a run starts at a word character whose predecessor does not continue a run; one thread
-//      walks each run, counts its code points and hashes them (64-bit FNV-1a with one round per
+//   3. a run starts at a word character whose predecessor does not continue a run; the run
+//      starts are compacted in byte order, then one thread per run walks it, counts its code
+//      points and hashes them (64-bit FNV-1a with one round per
 //      code point, finalised with the splitmix64 mixer); runs of two or more code points are the
 //      tokens;
 //   4. tokens go into an open-addressing hash table keyed by their hash; the table records each
@@ -190,36 +191,44 @@ struct Run {
   uint64_t hash;
 };
 
-// 2. one thread per run start walks the run (same document iteration as k_mark_runs).
-__global__ __launch_bounds__(kThreads) void k_walk_runs(TextView tv, const uint32_t* mark,
-                                                        const uint32_t* run_idx, Run* runs,
-                                                        uint32_t* keep) {
+// 2a. each run start's byte and document go to the run's slot (same document iteration as
+//     k_mark_runs).
+__global__ __launch_bounds__(kThreads) void k_run_starts(TextView tv, const uint32_t* mark,
+                                                         const uint32_t* run_idx, Run* runs) {
   for (int64_t d = blockIdx.x; d < tv.n_docs; d += gridDim.x) {
     const int64_t lo = tv.doc_off[d], hi = tv.doc_off[d + 1];
     for (int64_t i = lo + threadIdx.x; i < hi; i += kThreads) {
       if (!mark[i]) continue;
-      uint64_t h = 0xcbf29ce484222325ull;
-      uint32_t n = 0;
-      int64_t j = i;
-      while (j < hi) {
-        const Char c = char_at(tv.text, j, hi, tv.lower);
-        if (c.len == 0 || !c.word) break;
-        h = hash_step(h, c.cp);
-        ++n;
-        j += c.len;
-        if (!c.joins) break;
-      }
       const uint32_t r = run_idx[i];
-      Run run;
-      run.start = (uint32_t)i;
-      run.end = (uint32_t)j;
-      run.n_cp = n;
-      run.doc = (int32_t)d;
-      run.hash = hash_final(h);
-      runs[r] = run;
-      keep[r] = n >= 2 ? 1u : 0u;
+      runs[r].start = (uint32_t)i;
+      runs[r].doc = (int32_t)d;
     }
   }
+}
+
+// 2b. one thread per run walks it: consecutive lanes take consecutive runs, so a wave walks 64
+//     runs at once instead of the few that start in 64 consecutive bytes.
+__global__ __launch_bounds__(kThreads) void k_walk_runs(TextView tv, Run* runs, uint32_t* keep,
+                                                        int64_t n_runs) {
+  const int64_t r = (int64_t)blockIdx.x * kThreads + threadIdx.x;
+  if (r >= n_runs) return;
+  const int64_t i = runs[r].start;
+  const int64_t hi = tv.doc_off[runs[r].doc + 1];
+  uint64_t h = 0xcbf29ce484222325ull;
+  uint32_t n = 0;
+  int64_t j = i;
+  while (j < hi) {
+    const Char c = char_at(tv.text, j, hi, tv.lower);
+    if (c.len == 0 || !c.word) break;
+    h = hash_step(h, c.cp);
+    ++n;
+    j += c.len;
+    if (!c.joins) break;
+  }
+  runs[r].end = (uint32_t)j;
+  runs[r].n_cp = n;
+  runs[r].hash = hash_final(h);
+  keep[r] = n >= 2 ? 1u : 0u;
 }
 
 // 3. compaction of the tokens (runs of two or more code points).
@@ -539,9 +548,11 @@ static int split_text(const Alloc* al, const TextView& tv, int64_t n_bytes, hipS
   BM25_TALLOC(tok_idx, (size_t)std::max<uint32_t>(n_runs, 1) * 4);
   BM25_TALLOC(tmp2, (size_t)scan_tmp_elems(std::max<uint32_t>(n_runs, 1)) * 4 + 64);
   if (n_runs > 0) {
-    hipLaunchKernelGGL(k_walk_runs, dim3(doc_blocks(tv.n_docs)), dim3(kThreads), 0, s, tv,
-                       mark.as<uint32_t>(), run_idx.as<uint32_t>(), runs.as<Run>(),
-                       keep.as<uint32_t>());
+    hipLaunchKernelGGL(k_run_starts, dim3(doc_blocks(tv.n_docs)), dim3(kThreads), 0, s, tv,
+                       mark.as<uint32_t>(), run_idx.as<uint32_t>(), runs.as<Run>());
+    BM25_HIP(hipGetLastError());
+    hipLaunchKernelGGL(k_walk_runs, dim3(blocks_for(n_runs)), dim3(kThreads), 0, s, tv,
+                       runs.as<Run>(), keep.as<uint32_t>(), (int64_t)n_runs);
     BM25_HIP(hipGetLastError());
   }
   mark.release();
