@@ -50,15 +50,9 @@ __device__ __forceinline__ bool uni_word(uint32_t cp) {
 }
 
 __device__ __forceinline__ uint32_t uni_lower(uint32_t cp) {
-  int lo = 0, hi = kUniLowerPairs - 1;
-  while (lo <= hi) {
-    const int mid = (lo + hi) >> 1;
-    const uint32_t v = kUniLowerFrom[mid];
-    if (v == cp) return kUniLowerTo[mid];
-    if (v < cp) lo = mid + 1;
-    else hi = mid - 1;
-  }
-  return cp;
+  if (cp >= 0x110000u) return cp;
+  const uint32_t b = kUniLowerIndex[cp >> 7];
+  return b == 0 ? cp : (uint32_t)((int32_t)cp + kUniLowerDelta[b][cp & 127u]);
 }
 
 // Length (1..4) of the valid UTF-8 sequence starting at byte i of a document ending at `hi`, and
@@ -311,6 +305,14 @@ __global__ __launch_bounds__(kThreads) void k_insert(const Run* toks, int64_t n_
 // Code point by code point comparison of two tokens' words (after case mapping).
 __device__ bool same_word(const uint8_t* text, const Run& a, const Run& b, bool lower) {
   if (a.n_cp != b.n_cp) return false;
+  // most repeats are byte for byte the same text, which decodes and maps to the same code
+  // points; only spans that differ (case, with lowercasing) are compared code point by code point
+  const uint32_t len = a.end - a.start;
+  if (b.end - b.start == len) {
+    uint32_t x = 0;
+    while (x < len && text[(int64_t)a.start + x] == text[(int64_t)b.start + x]) ++x;
+    if (x == len) return true;
+  }
   int64_t i = a.start, j = b.start;
   for (uint32_t n = 0; n < a.n_cp; ++n) {
     const Char ca = char_at(text, i, a.end, lower);
